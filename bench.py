@@ -1,0 +1,151 @@
+"""Benchmark: batched exact division at 2^16 bits on one MI355X.
+
+One step = one mp_divrem_batch launch over the whole workload (every
+instance goes through shifted inverse, quotient product, remainder product
+and corrections).  Inputs are device-resident before the timed region.
+Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--config c2|c1|c3] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "divisions/sec at 2^16-bit u (bit-exact) + % int-mul roofline; serving p99 latency"
+
+# Integer-multiply roofline of MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz,
+# one 32x32->64-bit v_mad_u64_u32 per lane every 4 cycles (quarter rate).
+PEAK_LIMB_PRODUCTS = 256 * 4 * 16 * 2.4e9 / 4
+
+
+def prec_rows(x):
+    """number of significant limbs of each row"""
+    nz = x != 0
+    return np.where(nz.any(axis=1), x.shape[1] - np.argmax(nz[:, ::-1], axis=1), 0)
+
+
+def workload(name):
+    from paper_2606_06386_amd import inputs as I
+    return {"c1": I.config_c1, "c2": I.config_c2, "c3": I.config_c3}[name]()
+
+
+def limb_products(u, v):
+    """Algorithmic limb products of one launch over the batch (cost model W)."""
+    from paper_2606_06386_amd import costmodel as cm
+    hs, nvs = prec_rows(u), prec_rows(v)
+    total = 0
+    cache = {}
+    for h, nvv in zip(hs.tolist(), nvs.tolist()):
+        key = (h, nvv - 1)
+        if key not in cache:
+            cache[key] = cm.division_cost(h, nvv - 1) if nvv >= 2 and h >= nvv else 0
+        total += cache[key]
+    return total
+
+
+def cpu_baseline(c, q_gpu, r_gpu, budget_s=10.0):
+    """The oracle (plain C, OpenMP over instances) on a bounded sample of the
+    same workload; also checks the GPU results of the sample bit-exactly."""
+    import oracle
+    u, v, nq = c["u"], c["v"], c["nq"]
+    n = 32
+    t0 = time.perf_counter()
+    oracle.divrem_threads(u[:n], v[:n], nq, v.shape[1])
+    t = time.perf_counter() - t0
+    n = int(min(len(u), max(n, n * budget_s / max(t, 1e-3))))
+    t0 = time.perf_counter()
+    qo, ro, so, used = oracle.divrem_threads(u[:n], v[:n], nq, v.shape[1])
+    t = time.perf_counter() - t0
+    exact = int(((qo == q_gpu[:n]).all(axis=1) & (ro == r_gpu[:n]).all(axis=1)).sum())
+    return {"value": n / t, "unit": "div/s", "cores": int(used), "kind": "oracle",
+            "sample": f"first {n} of {len(u)} instances of {c['name']} (Knuth D, gcc -O2, OpenMP)"}, exact, n
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: every division instance is independent and this "
+              "build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_06386_amd import binding
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    c = workload(args.config)
+    u_h, v_h, nq = c["u"], c["v"], c["nq"]
+    batch = len(u_h)
+    u = torch.from_numpy(u_h.view(np.int32)).to(dev)
+    v = torch.from_numpy(v_h.view(np.int32)).to(dev)
+    q = torch.empty((batch, nq), dtype=torch.int32, device=dev)
+    r = torch.empty((batch, v_h.shape[1]), dtype=torch.int32, device=dev)
+    st = torch.empty(batch, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        binding.divrem(u, v, out=(q, r, st), stream=stream)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        binding.divrem(u, v, out=(q, r, st), stream=stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
+    kmean = sum(kernel_ms) / len(kernel_ms)
+
+    status = st.cpu().numpy()
+    q_h, r_h = q.cpu().numpy().view(np.uint32), r.cpu().numpy().view(np.uint32)
+    W = limb_products(u_h, v_h)
+    achieved = W / (kmean * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": batch * args.steps / elapsed,
+        "unit": "div/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": c["name"], "bits": c["bits"], "batch": batch, "nu": int(u_h.shape[1]),
+                   "nv": int(v_h.shape[1]), "nq": nq},
+        "kernel_ms": {"mean": kmean, "median": kernel_ms[len(kernel_ms) // 2], "min": kernel_ms[0]},
+        "limb_products_per_launch": W,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LIMB_PRODUCTS / 1e12,
+                     "unit": "T limb-products/s", "frac": achieved / PEAK_LIMB_PRODUCTS, "traffic": None,
+                     "kernel": "k_divrem"},
+        "status_ok": int((status == 0).sum()),
+    }
+    if not args.no_cpu_baseline:
+        cb, exact, n = cpu_baseline(c, q_h, r_h)
+        line["cpu_baseline"] = cb
+        line["parity_sample"] = f"{exact}/{n} bit-exact vs oracle"
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

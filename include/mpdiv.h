@@ -1,0 +1,98 @@
+/*
+ * mpdiv.h -- batched exact multi-precision integer division on MI355X (gfx950).
+ *
+ * The library computes, for many independent instances at once, the
+ * operations of the shifted-inverse division method of Marchioro, Raahauge,
+ * Lovenskjold, Oancea and Watt, "On GPU Implementation for Multi-Precision
+ * Integer Division" (Watt's whole-shifted-inverse Newton iteration):
+ *
+ *   mp_mul_batch     c = a * b                     (the method's Mult; Alg. 2, 3)
+ *   mp_shinv_batch   w = shinv_h(v) = floor(B^h/v) (Definition 1; Alg. 1)
+ *   mp_divrem_batch  (q, r): u = q*v + r, 0<=r<v   (Alg. 3 with Thm. 2's correction)
+ *
+ * Representation: base B = 2^32.  A number is a little-endian array of
+ * uint32_t limbs; limb i has weight B^i.  Leading zero limbs are allowed in
+ * every input (each instance's effective precision is found on the device).
+ * A batch of L-limb operands is dense and row-major: instance j starts at
+ * p + (size_t)j * L.
+ *
+ * Memory: every data pointer is a DEVICE pointer (for example a torch tensor's
+ * data_ptr()).  The library never allocates, frees or keeps caller memory.
+ * Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL is
+ * the default stream); the caller synchronises before reading results.  Calls
+ * on one stream are ordered; outputs must not overlap inputs.
+ *
+ * Errors: argument errors are detected on the host and returned before
+ * anything is launched; a failed launch returns MP_ERR_LAUNCH.  Per-instance
+ * outcomes are written to inst_status[j] (may be NULL):
+ *   MP_INST_OK        result written;
+ *   MP_INST_DIVZERO   v = 0: every output limb of the instance is 0;
+ *   MP_INST_QWIDTH    the quotient (or shifted inverse) needs more limbs than
+ *                     the output width: every output limb of the instance is 0;
+ *   MP_INST_INTERNAL  an internal bound of the method was exceeded (not
+ *                     expected for any input): outputs are 0.
+ */
+#ifndef MPDIV_H
+#define MPDIV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MP_OK = 0,          /* launched (or nothing to do: batch == 0) */
+    MP_ERR_ARG = 1,     /* null pointer, non-positive width, negative batch */
+    MP_ERR_SIZE = 2,    /* an operand width exceeds mp_max_limbs() */
+    MP_ERR_LAUNCH = 3,  /* the HIP launch failed */
+    MP_ERR_DEVICE = 4   /* no usable gfx950 device */
+} mp_status_t;
+
+enum { MP_INST_OK = 0, MP_INST_DIVZERO = 1, MP_INST_QWIDTH = 2, MP_INST_INTERNAL = 3 };
+
+/*
+ * c = a * b for each instance: the classical (schoolbook) product, the
+ * multiplication the method is parameterised by (Sec. 3.3).
+ *   a: batch x na limbs, b: batch x nb limbs, c: batch x (na + nb) limbs.
+ *   1 <= na, nb <= mp_max_limbs().
+ */
+mp_status_t mp_mul_batch(const uint32_t *a, int32_t na, const uint32_t *b, int32_t nb,
+                         uint32_t *c, int32_t batch, void *stream);
+
+/*
+ * w = floor(B^h / v) for each instance, exactly (Definition 1, computed by
+ * Alg. 1 and corrected to the exact value).
+ *   v: batch x nv limbs (1 <= nv <= mp_max_limbs()), h: 0 <= h <= mp_max_limbs(),
+ *   w: batch x nw limbs, zero-padded; nw >= h - prec(v) + 2 always suffices
+ *   (h + 1 for any v).
+ *   inst_status: batch int32 or NULL.
+ */
+mp_status_t mp_shinv_batch(const uint32_t *v, int32_t nv, int32_t h, uint32_t *w, int32_t nw,
+                           int32_t *inst_status, int32_t batch, void *stream);
+
+/*
+ * Quotient and remainder of u by v for each instance (Alg. 3: the quotient
+ * from u times the shifted inverse of v, then at most one downward and two
+ * upward corrections).
+ *   u: batch x nu limbs, v: batch x nv limbs, 1 <= nu, nv <= mp_max_limbs();
+ *   q: batch x nq limbs, zero-padded; nq >= nu - prec(v) + 1 suffices (nu always);
+ *   r: batch x nv limbs, zero-padded;
+ *   inst_status: batch int32 or NULL.
+ * u = 0 gives (0, 0); u < v gives (0, u).
+ */
+mp_status_t mp_divrem_batch(const uint32_t *u, int32_t nu, const uint32_t *v, int32_t nv,
+                            uint32_t *q, int32_t nq, uint32_t *r, int32_t *inst_status,
+                            int32_t batch, void *stream);
+
+/* human-readable name of a status code (static storage) */
+const char *mp_status_str(mp_status_t s);
+
+/* largest operand width in limbs any entry point accepts (8192 = 2^18 bits) */
+int32_t mp_max_limbs(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPDIV_H */

@@ -1,0 +1,437 @@
+// One multi-precision product, shifted inverse or division per workgroup.
+//
+// The division is the paper's shifted-inverse method:
+//   Alg. 1 (Shinv): special cases, 2-limb initial approximation
+//                   w = floor(B^3 / (v_{k-1} + v_k B)), then Refine: Newton
+//                   steps with shorter iterates (l doubling) and divisor
+//                   prefixes (v >> s limbs), 2 guard limbs.
+//   Alg. 1 (Step):  w' = shift_m(w) +- shift_{2m-H}(w * x), the negative
+//                   branch rounded toward -infinity.
+//   Alg. 2 (PowDiff): (sign, |B^h - v w|) from the full product, or from the
+//                   low L limbs of v w (the close product).
+//   Alg. 3 (Div):   q = shift_{-h}(u * shinv_h(v)), m = v q, then quotient
+//                   corrections.
+// All numbers are little-endian base B = 2^32 limbs; h, k, l, m, s, g count
+// limbs.  Readings taken where the printed algorithms are silent or garbled:
+//   * the Refine loop runs 2 + ceil(log2(h-k-1)) times, 2 times when
+//     h-k-1 <= 1;
+//   * Step's rounding test looks at the h-2m (not 2m-h) low limbs of w*x;
+//   * PowDiff's sign is 1 iff B^h - v*w >= 0;
+//   * the computed inverse can be floor(B^h/v) - 1 as well as + 1, so the
+//     division allows one downward and two upward quotient corrections, and
+//     the stand-alone shinv ends with an exact one-step fix-up.
+#pragma once
+
+#include <stdint.h>
+
+namespace mp {
+
+enum : int32_t { kInstOk = 0, kInstDivZero = 1, kInstQWidth = 2, kInstInternal = 3 };
+
+#define MP_HD __host__ __device__ __forceinline__
+
+MP_HD int r4(int x) { return (x + 3) & ~3; }
+MP_HD int hmax(int a, int b) { return a > b ? a : b; }
+
+// LDS layout of one division / shifted-inverse instance with h = prec(u)
+// (or the shinv precision) and k = prec(v) - 1, in 32-bit words.  Capacities
+// bound every intermediate of the method: w <= h-k+4 limbs, x <= k+8,
+// Refine products <= h+6, u*shinv <= 2h-k+1, shinv <= h-k+1.
+struct Plan {
+    int capV, capW, capX, capSB, capP;
+    int offV, offW, offX, offSB, offP;   // offSB: limb 0 of the staged window
+    int total;
+};
+
+MP_HD Plan plan_div(int h, int k)
+{
+    Plan p;
+    const int d = h - k;
+    p.capV = r4(k + 1);
+    p.capW = r4(d + 8);
+    p.capX = r4(k + 12);
+    p.capSB = r4(hmax(hmax(h, k + 12), d + 8) + 4);
+    p.capP = r4(hmax(2 * h - k + 1, h + 8) + 4);
+    p.offV = kCtlWords;
+    p.offW = p.offV + p.capV;
+    p.offX = p.offW + p.capW;
+    p.offSB = p.offX + p.capX + kPad;
+    p.offP = p.offSB + p.capSB + kPad;
+    p.total = p.offP + p.capP + 4;
+    return p;
+}
+
+// words needed by the single-limb-divisor path (quotient + chunk scratch)
+MP_HD int plan_short_words(int n, int T) { return kCtlWords + 2 * T + r4(n + 1) + 4; }
+
+// LDS words for a batch whose dividends have at most nu limbs and divisors at
+// most nv limbs (every (h, k) an instance can reach)
+MP_HD int div_lds_words(int nu, int nv, int T)
+{
+    int best = plan_short_words(nu, T);
+    const int kmax = (nv < nu ? nv : nu) - 1;
+    for (int k = 1; k <= kmax; k++) best = hmax(best, plan_div(nu, k).total);
+    return best;
+}
+
+MP_HD int mul_lds_words(int na, int nb)
+{
+    const int lo = na < nb ? na : nb, hi = na < nb ? nb : na;
+    return kCtlWords + r4(lo) + 4 + kPad + r4(hi) + kPad + r4(na + nb) + 4;
+}
+
+// ------------------------------------------------------------------ helpers
+
+// p[0, ncols) = x*y mod B^ncols: the longer operand is staged as the window
+template <int T>
+MP_DEV void product(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *x, int nx,
+                    const uint32_t *y, int ny, uint32_t *sb, int &sbext)
+{
+    const uint32_t *rows = nx >= ny ? y : x, *win = nx >= ny ? x : y;
+    const int nr = nx >= ny ? ny : nx, nwin = nx >= ny ? nx : ny;
+    copy<T>(sb, nwin, sbext, Span{win, 0, nwin});
+    sbext = nwin;
+    mul<T>(ctl, p, ncols, rows, nr, sb, nwin);
+}
+
+// dst[0, n) = src limbs [0, e) zero-padded, where e = prec(src) must be <= n;
+// returns false (and stores nothing) when the value needs more than n limbs
+template <int T, class FS>
+MP_DEV bool store_fit(uint32_t *ctl, uint32_t *dst, int n, int ext, const FS &src)
+{
+    const int e = prec<T>(ctl, ext, src);
+    if (e > n) return false;
+    for (int i = tid(); i < n; i += T) dst[i] = i < e ? src(i) : 0u;
+    return true;
+}
+
+template <int T>
+MP_DEV void store_zero(uint32_t *dst, int n)
+{
+    for (int i = tid(); i < n; i += T) dst[i] = 0u;
+}
+
+MP_DEV int ceil_log2(int x)   // x >= 1
+{
+    int r = 0;
+    while ((1 << r) < x) r++;
+    return r;
+}
+
+// ------------------------------------------------------- Alg. 1 Refine
+
+// Initial approximation and the Refine loop for B^k <= v < B^(k+1), k >= 1,
+// h - k >= 1, B < v <= B^h / 2, v not a power of B.  v is in V (k+1 limbs).
+// On return the shifted inverse is the limbs of W above `shf`, with W's
+// nonzero limbs inside [0, we).  Returns false if a capacity guard trips or
+// a Step result turns negative (never expected).
+template <int T>
+MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, int &we, int &shf,
+                   int &sbext)
+{
+    uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
+    uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP;
+    const int g = 2, d = h - k;
+    // w = shift_g(floor(B^3 / V)), V = v_{k-1} + v_k B; w0 <= B^2 has 3 limbs
+    sync();
+    if (tid() == 0) {
+        const uint64_t Vt = ((uint64_t)V[k] << 32) | V[k - 1];
+        const unsigned __int128 w0 = (((unsigned __int128)1) << 96) / Vt;
+        W[0] = 0u;
+        W[1] = 0u;
+        W[2] = (uint32_t)w0;
+        W[3] = (uint32_t)(w0 >> 32);
+        W[4] = (uint32_t)(w0 >> 64);
+    }
+    we = 5;
+    int l = 2;
+    const int iters = 2 + (d - 1 <= 1 ? 0 : ceil_log2(d - 1));
+    for (int i = 0; i < iters; i++) {
+        const int m = imin(d + 1 - l, l);
+        const int s = imax(0, k - 2 * l + 1 - g);
+        const int H = k + l + m - s + g;
+        const uint32_t *vp = V + s;          // divisor prefix shift_{-s}(v)
+        const int nvp = k + 1 - s;
+        const int hp = H - m, lp = l - g;   // PowDiff(v', w, H - m, l - g)
+        const int nw = prec<T>(ctl, we, Span{W, 0, we});
+        const int L = nvp + nw - lp + 1;
+        bool sign;
+        int nxb;
+        if (L >= hp) {                      // full product, compare with B^hp
+            const int np0 = nvp + nw;
+            if (np0 > pl.capP) return false;
+            product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext);
+            const int np = prec<T>(ctl, np0, Span{P, 0, np0});
+            if (np <= hp) {                 // P < B^hp: x = B^hp - P
+                if (hp > pl.capX) return false;
+                sign = true;
+                nxb = hp;
+                addsub<T>(ctl, hp, true, 0u, Zero{}, Span{P, 0, np}, Store{X, 0, hp});
+            } else {                        // x = P - B^hp
+                if (np > pl.capX) return false;
+                sign = false;
+                nxb = np;
+                addsub<T>(ctl, np, true, 0u, Span{P, 0, np}, PowB{hp}, Store{X, 0, np});
+            }
+        } else {                            // close product: P = v'w mod B^L
+            if (L > pl.capP || L > pl.capX) return false;
+            product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext);
+            const int np = prec<T>(ctl, L, Span{P, 0, L});
+            if (np == 0) {                  // v'w = B^hp exactly
+                sign = true;
+                nxb = 0;
+            } else if (np < L) {            // top limb 0: v'w = B^hp + P
+                sign = false;
+                nxb = np;
+                copy<T>(X, np, 0, Span{P, 0, np});
+            } else {                        // v'w = B^hp - (B^L - P)
+                sign = true;
+                nxb = L;
+                addsub<T>(ctl, L, true, 0u, Zero{}, Span{P, 0, L}, Store{X, 0, L});
+            }
+        }
+        const int nx = nxb ? prec<T>(ctl, nxb, Span{X, 0, nxb}) : 0;
+        // Step: res = shift_m(w) +- shift_{2m-H}(w x); then w = shift_{-post}(res)
+        const int sh = H - 2 * m;
+        const int post = i < 2 ? m : 1;
+        int nt = 0;
+        if (nx) {
+            nt = nw + nx;
+            if (nt > pl.capP) return false;
+            product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext);
+        }
+        uint32_t sticky = 0;
+        if (!sign && nt > 0) {
+            const int top = imin(sh, nt);
+            sticky = reduce_max<T>(ctl, top, [&](int j) -> uint32_t { return P[j] ? 1u : 0u; });
+        }
+        const int nres = imax(nw + m, nt - sh) + 1;
+        if (nres - post > pl.capW) return false;
+        const uint32_t co = addsub<T>(ctl, nres, !sign, sticky, Span{W, m, nw}, Span{P, -sh, imax(nt, 0)},
+                                      Store{W, post, pl.capW});
+        if (!sign && co) return false;
+        we = nres - post;
+        if (i >= 2) l = l + m - 1;
+    }
+    shf = d < 2 ? 4 - d : 2;
+    return true;
+}
+
+// ------------------------------------------------------------ instances
+
+// c = a * b  (c has na + nb limbs)
+template <int T>
+MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_t *b, int nb, uint32_t *c)
+{
+    uint32_t *ctl = lds;
+    const int nlo = na < nb ? na : nb, nhi = na < nb ? nb : na;
+    const uint32_t *rows = na < nb ? a : b, *win = na < nb ? b : a;
+    uint32_t *A = lds + kCtlWords;
+    uint32_t *SBbase = A + r4(nlo) + 4;
+    uint32_t *SB = SBbase + kPad;
+    uint32_t *P = SB + r4(nhi) + kPad;
+    copy<T>(A, nlo, r4(nlo) + 4, Span{rows, 0, nlo});
+    copy<T>(SBbase, kPad + nhi, 2 * kPad + r4(nhi), Span{win, kPad, nhi});
+    mul<T>(ctl, P, na + nb, A, nlo, SB, nhi);
+    sync();
+    for (int i = tid(); i < na + nb; i += T) c[i] = P[i];
+}
+
+// w = floor(B^h / v), exactly (nw limbs)
+template <int T>
+MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint32_t *w, int nw,
+                           int32_t *status)
+{
+    uint32_t *ctl = lds;
+    const Span Vg{v, 0, nv};
+    int32_t st = kInstOk;
+    const int nvv = prec<T>(ctl, nv, Vg);
+    if (nvv == 0) {
+        store_zero<T>(w, nw);
+        if (status && tid() == 0) *status = kInstDivZero;
+        return;
+    }
+    const int k = nvv - 1;
+    const int lowz = prec<T>(ctl, k, Vg) == 0;   // limbs below k all zero
+    const uint32_t vk = v[k];
+    bool ok = true;
+    if (k == 0) {                                 // v < B: B^h quo v by short division
+        uint32_t *scratch = lds + kCtlWords, *Q = scratch + 2 * T;
+        shortdiv<T>(ctl, scratch, h + 1, PowB{h}, vk, Store{Q, 0, h + 1});
+        ok = store_fit<T>(ctl, w, nw, h + 1, Span{Q, 0, h + 1});
+    } else if (k > h || (k == h && !(lowz && vk == 1u))) {   // v > B^h
+        store_zero<T>(w, nw);
+    } else if (k == h ||                                      // v = B^h
+               (k == h - 1 && (vk > 0x80000000u || (vk == 0x80000000u && !lowz)))) {  // 2v > B^h
+        ok = nw >= 1;
+        if (ok)
+            for (int i = tid(); i < nw; i += T) w[i] = i == 0 ? 1u : 0u;
+    } else if (lowz && vk == 1u) {                            // v = B^k: B^(h-k)
+        ok = nw > h - k;
+        if (ok) {
+            const int e = h - k;
+            for (int i = tid(); i < nw; i += T) w[i] = i == e ? 1u : 0u;
+        }
+    } else {
+        const Plan pl = plan_div(h, k);
+        uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
+        uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP;
+        copy<T>(V, k + 1, 0, Vg);
+        copy<T>(W, 0, pl.capW, Zero{});
+        copy<T>(SB - kPad, 0, pl.capSB + 2 * kPad, Zero{});
+        int we = 0, shf = 0, sbext = 0;
+        if (!refine<T>(ctl, pl, lds, h, k, we, shf, sbext)) {
+            st = kInstInternal;
+        } else {
+            // exact fix-up: D = B^h - v*s with s within one of floor(B^h/v)
+            uint32_t *S = W + shf;
+            int se = imax(we - shf, 0);
+            const int ns = prec<T>(ctl, se, Span{S, 0, se});
+            const int d = h - k;
+            int adj = 0;
+            if (d >= 3) {
+                const int L = k + 3;            // |D| < 2v < B^(k+2) and B^h = 0 mod B^L
+                product<T>(ctl, P, L, V, k + 1, S, ns, SB, sbext);
+                const int np = prec<T>(ctl, L, Span{P, 0, L});
+                sync();
+                const uint32_t top = P[L - 1];
+                if (np > 0 && top == 0u) {
+                    adj = -1;                   // D = -P < 0
+                } else if (np > 0) {            // D = B^L - P > 0
+                    addsub<T>(ctl, L, true, 0u, Zero{}, Span{P, 0, L}, Store{X, 0, L});
+                    if (cmp<T>(ctl, L, Span{X, 0, L}, Span{V, 0, k + 1}) >= 0) adj = 1;
+                }
+            } else {
+                const int np0 = k + 1 + ns;     // small inverse: full product
+                product<T>(ctl, P, np0, V, k + 1, S, ns, SB, sbext);
+                const int n = imax(np0, h + 1);
+                const int c = cmp<T>(ctl, n, Span{P, 0, np0}, PowB{h});
+                if (c > 0) {
+                    adj = -1;
+                } else if (c < 0) {
+                    addsub<T>(ctl, h, true, 0u, Zero{}, Span{P, 0, np0}, Store{X, 0, h});
+                    if (cmp<T>(ctl, h, Span{X, 0, h}, Span{V, 0, k + 1}) >= 0) adj = 1;
+                }
+            }
+            if (adj != 0) {
+                addsub<T>(ctl, se + 1, adj < 0, 1u, Span{S, 0, se}, Zero{}, Store{S, 0, se + 1});
+                se += 1;
+            }
+            ok = store_fit<T>(ctl, w, nw, se, Span{S, 0, se});
+        }
+    }
+    if (st == kInstOk && !ok) st = kInstQWidth;
+    if (st != kInstOk) {
+        sync();
+        store_zero<T>(w, nw);
+    }
+    if (status && tid() == 0) *status = st;
+}
+
+// (q, r) with u = q v + r, 0 <= r < v  (q: nq limbs, r: nv limbs)
+template <int T>
+MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint32_t *v, int nv,
+                            uint32_t *q, int nq, uint32_t *r, int32_t *status)
+{
+    uint32_t *ctl = lds;
+    const Span Ug{u, 0, nu}, Vg{v, 0, nv};
+    int32_t st = kInstOk;
+    bool ok = true;
+    const int h = prec<T>(ctl, nu, Ug);
+    const int nvv = prec<T>(ctl, nv, Vg);
+    if (nvv == 0) {
+        store_zero<T>(q, nq);
+        store_zero<T>(r, nv);
+        if (status && tid() == 0) *status = kInstDivZero;
+        return;
+    }
+    const int c0 = h < nvv ? -1 : (h > nvv ? 1 : cmp<T>(ctl, h, Ug, Vg));
+    const int k = nvv - 1;
+    if (c0 < 0) {                                 // u < v: (0, u)
+        store_zero<T>(q, nq);
+        for (int i = tid(); i < nv; i += T) r[i] = i < h ? u[i] : 0u;
+        if (status && tid() == 0) *status = kInstOk;
+        return;
+    }
+    const int lowz = k > 0 && prec<T>(ctl, k, Vg) == 0;
+    const uint32_t vk = v[k];
+    if (k == 0) {                                 // single-limb divisor: short division of u
+        uint32_t *scratch = lds + kCtlWords, *Q = scratch + 2 * T;
+        const uint32_t rem = shortdiv<T>(ctl, scratch, h, Ug, vk, Store{Q, 0, h});
+        ok = store_fit<T>(ctl, q, nq, h, Span{Q, 0, h});
+        if (ok)
+            for (int i = tid(); i < nv; i += T) r[i] = i == 0 ? rem : 0u;
+    } else if (lowz && vk == 1u) {                // v = B^k: shinv = B^(h-k), q = u >> k
+        ok = store_fit<T>(ctl, q, nq, h - k, Span{u, -k, h});
+        if (ok)
+            for (int i = tid(); i < nv; i += T) r[i] = i < k ? u[i] : 0u;
+    } else {
+        const Plan pl = plan_div(h, k);
+        uint32_t *V = lds + pl.offV, *W = lds + pl.offW;
+        uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP;
+        copy<T>(V, k + 1, 0, Vg);
+        copy<T>(W, 0, pl.capW, Zero{});
+        copy<T>(SB - kPad, 0, pl.capSB + 2 * kPad, Zero{});
+        int we = 0, shf = 0, sbext = 0;
+        bool good = true;
+        if (k == h - 1 && (vk > 0x80000000u || (vk == 0x80000000u && !lowz))) {
+            sync();                               // 2v > B^h: shinv = 1
+            if (tid() == 0) W[0] = 1u;
+            we = 1;
+            shf = 0;
+        } else {
+            good = refine<T>(ctl, pl, lds, h, k, we, shf, sbext);
+        }
+        if (good) {
+            // q0 = shift_{-h}(u * s)
+            const uint32_t *S = W + shf;
+            const int se = imax(we - shf, 0);
+            const int ns = prec<T>(ctl, se, Span{S, 0, se});
+            good = ns <= h;
+            if (good) {
+                copy<T>(SB, h, sbext, Ug);
+                sbext = h;
+                mul<T>(ctl, P, h + ns, S, ns, SB, h);
+                copy<T>(W, ns, we, Span{P, -h, h + ns});
+                we = ns;
+                const int nq0 = prec<T>(ctl, we, Span{W, 0, we});
+                // m = v * q0
+                const int ml = nq0 + k + 1;
+                product<T>(ctl, P, ml, W, nq0, V, k + 1, SB, sbext);
+                const int nc = imax(h, ml);
+                if (cmp<T>(ctl, nc, Ug, Span{P, 0, ml}) < 0) {        // u < m: q0 - 1, m - v
+                    const uint32_t b = addsub<T>(ctl, we, true, 1u, Span{W, 0, we}, Zero{}, Store{W, 0, we});
+                    addsub<T>(ctl, ml, true, 0u, Span{P, 0, ml}, Span{V, 0, k + 1}, Store{P, 0, ml});
+                    good = b == 0u;
+                }
+                // r = u - m (no borrow over all limbs of both: r <= u < B^h),
+                // then up to two upward corrections
+                uint32_t *R = SB;
+                const uint32_t bo = addsub<T>(ctl, nc, true, 0u, Ug, Span{P, 0, ml}, Store{R, 0, h});
+                good = good && bo == 0u;
+                for (int it = 0; it < 3 && good; it++) {
+                    if (cmp<T>(ctl, h, Span{R, 0, h}, Span{V, 0, k + 1}) < 0) break;
+                    if (it == 2) { good = false; break; }
+                    addsub<T>(ctl, we + 1, false, 1u, Span{W, 0, we}, Zero{}, Store{W, 0, we + 1});
+                    we += 1;
+                    addsub<T>(ctl, h, true, 0u, Span{R, 0, h}, Span{V, 0, k + 1}, Store{R, 0, h});
+                }
+                if (good) {
+                    ok = store_fit<T>(ctl, q, nq, we, Span{W, 0, we});
+                    if (ok)
+                        for (int i = tid(); i < nv; i += T) r[i] = i < k + 1 ? R[i] : 0u;
+                }
+            }
+        }
+        if (!good) st = kInstInternal;
+    }
+    if (st == kInstOk && !ok) st = kInstQWidth;
+    if (st != kInstOk) {
+        sync();
+        store_zero<T>(q, nq);
+        store_zero<T>(r, nv);
+    }
+    if (status && tid() == 0) *status = st;
+}
+
+}  // namespace mp

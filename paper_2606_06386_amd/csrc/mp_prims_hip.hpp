@@ -1,0 +1,76 @@
+// Workgroup and wavefront primitives for gfx950 (CDNA4, wave64).
+//
+// The multi-precision code in mp_core.hpp / mp_div.hpp is written against
+// exactly this small set of operations: thread index, workgroup barrier,
+// wave ballot / shuffles, a wave-uniform broadcast, and the 4x4 block of
+// 32x32->64-bit multiply-accumulates that dominates every product.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MP_DEV __device__ __forceinline__
+
+namespace mp {
+
+constexpr int kLanes = 64;  // CDNA wavefront width
+
+MP_DEV int tid() { return (int)threadIdx.x; }
+MP_DEV int lane() { return (int)(threadIdx.x & (kLanes - 1)); }
+MP_DEV void sync() { __syncthreads(); }
+MP_DEV uint64_t ballot(bool p) { return __ballot(p); }
+
+// value held by lane-1 (lane 0 receives 0)
+MP_DEV uint32_t shfl_up1(uint32_t x)
+{
+    uint32_t y = __shfl_up(x, 1);
+    return lane() == 0 ? 0u : y;
+}
+
+MP_DEV uint32_t shfl_xor(uint32_t x, int m) { return __shfl_xor(x, m); }
+
+// a value every lane of the wave already agrees on, moved to a scalar register
+MP_DEV uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+MP_DEV int uniform(int x) { return (int)__builtin_amdgcn_readfirstlane((uint32_t)x); }
+
+// acc[r] += a * b[r] for r = 0..3, each acc a 96-bit column sum held as a
+// 64-bit low part and a 32-bit high part.  v_mad_u64_u32 forms a*b + lo with
+// the carry out in an SGPR pair; v_addc folds the carry into hi.  On gfx950 a
+// VALU carry write needs two wait states before a VALU reads it; the three
+// independent multiplies placed between each write and its read provide them.
+MP_DEV void mac4(uint64_t (&lo)[4], uint32_t (&hi)[4], uint32_t a,
+                 uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3)
+{
+    uint64_t c0, c1, c2, c3;
+    asm volatile(
+        "v_mad_u64_u32 %0, %8, %12, %13, %0\n\t"
+        "v_mad_u64_u32 %1, %9, %12, %14, %1\n\t"
+        "v_mad_u64_u32 %2, %10, %12, %15, %2\n\t"
+        "v_mad_u64_u32 %3, %11, %12, %16, %3\n\t"
+        "v_addc_co_u32_e64 %4, %8, 0, %4, %8\n\t"
+        "v_addc_co_u32_e64 %5, %9, 0, %5, %9\n\t"
+        "v_addc_co_u32_e64 %6, %10, 0, %6, %10\n\t"
+        "v_addc_co_u32_e64 %7, %11, 0, %7, %11"
+        : "+v"(lo[0]), "+v"(lo[1]), "+v"(lo[2]), "+v"(lo[3]),
+          "+v"(hi[0]), "+v"(hi[1]), "+v"(hi[2]), "+v"(hi[3]),
+          "=&s"(c0), "=&s"(c1), "=&s"(c2), "=&s"(c3)
+        : "v"(a), "v"(b0), "v"(b1), "v"(b2), "v"(b3));
+}
+
+// 16-byte LDS/global vector load and store of four limbs
+struct Limb4 {
+    uint32_t x, y, z, w;
+};
+
+MP_DEV Limb4 load4(const uint32_t *p)
+{
+    uint4 v = *reinterpret_cast<const uint4 *>(p);
+    return Limb4{v.x, v.y, v.z, v.w};
+}
+
+MP_DEV void store4(uint32_t *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    *reinterpret_cast<uint4 *>(p) = make_uint4(a, b, c, d);
+}
+
+}  // namespace mp

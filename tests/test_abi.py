@@ -1,0 +1,84 @@
+"""The C-ABI library (CPU only: no compute call is made here).
+
+It loads, exports every entry point include/mpdiv.h declares, and rejects
+invalid arguments on the host before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mpdiv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mp_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_06386_amd import binding
+    return binding.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert set(names) == {"mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_status_str", "mp_max_limbs"}
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2606_06386_amd import binding
+    assert set(binding.EXPORTS) == set(names)
+
+
+def test_limits_and_status_strings(L):
+    assert L.mp_max_limbs() == 8192
+    for code in range(5):
+        assert L.mp_status_str(code).decode().startswith("MP_")
+
+
+def test_host_argument_errors(L):
+    from paper_2606_06386_amd.binding import MP_ERR_ARG, MP_ERR_SIZE, MP_OK
+    p = ctypes.c_void_p(16)   # never dereferenced: every call below returns before a launch
+    assert L.mp_divrem_batch(None, 4, p, 4, p, 4, p, None, 1, None) == MP_ERR_ARG
+    assert L.mp_divrem_batch(p, 0, p, 4, p, 4, p, None, 1, None) == MP_ERR_ARG
+    assert L.mp_divrem_batch(p, 4, p, 4, p, 0, p, None, 1, None) == MP_ERR_ARG
+    assert L.mp_divrem_batch(p, 4, p, 4, p, 4, p, None, -1, None) == MP_ERR_ARG
+    assert L.mp_divrem_batch(p, 8193, p, 4, p, 4, p, None, 1, None) == MP_ERR_SIZE
+    assert L.mp_divrem_batch(p, 4, p, 4, p, 4, p, None, 0, None) == MP_OK
+    assert L.mp_mul_batch(p, 4, None, 4, p, 1, None) == MP_ERR_ARG
+    assert L.mp_mul_batch(p, 9000, p, 4, p, 1, None) == MP_ERR_SIZE
+    assert L.mp_mul_batch(p, 4, p, 4, p, 0, None) == MP_OK
+    assert L.mp_shinv_batch(p, 4, -1, p, 4, None, 1, None) == MP_ERR_ARG
+    assert L.mp_shinv_batch(p, 4, 8193, p, 4, None, 1, None) == MP_ERR_SIZE
+    assert L.mp_shinv_batch(p, 4, 10, p, 11, None, 0, None) == MP_OK
+
+
+def test_lds_plan_bounds():
+    """The per-instance LDS plan (mirrored here from mp_div.hpp's plan_div for
+    the host-side size check) stays within gfx950's 160 KB at 2^18 bits."""
+    from paper_2606_06386_amd import costmodel  # noqa: F401  (importable without a GPU)
+    pad, ctl = 264, 256
+    r4 = lambda x: (x + 3) & ~3
+    worst = 0
+    h = 8192
+    for k in range(1, h):
+        d = h - k
+        tot = (ctl + r4(k + 1) + r4(d + 8) + r4(k + 12) + pad + r4(max(h, k + 12, d + 8) + 4) + pad
+               + r4(max(2 * h - k + 1, h + 8) + 4) + 4)
+        worst = max(worst, tot)
+    assert worst * 4 <= 160 * 1024
+
+
+def test_cost_model_values():
+    from paper_2606_06386_amd import costmodel as cm
+    # u*shinv and v*q are at least h*d + (k+1)*d; Refine adds less than both
+    for h, k in [(1024, 511), (2048, 1023), (8192, 2047)]:
+        d = h - k
+        base = h * d + (k + 1) * d
+        w = cm.division_cost(h, k)
+        assert base < w < 2 * base
+    assert cm.division_cost(2048, 1023) == 4391342
+    assert cm.low_product_cost(3, 5, 7) == 15 and cm.low_product_cost(3, 5, 2) == 3
+    assert cm.division_cost(10, 10) == 0 and cm.division_cost(10, 0) == 0
