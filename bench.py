@@ -21,9 +21,11 @@ if ROOT not in sys.path:
 
 METRIC = "divisions/sec at 2^16-bit u (bit-exact) + % int-mul roofline; serving p99 latency"
 
-# Integer-multiply roofline of MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz,
-# one 32x32->64-bit v_mad_u64_u32 per lane every 4 cycles (quarter rate).
-PEAK_LIMB_PRODUCTS = 256 * 4 * 16 * 2.4e9 / 4
+# Integer-multiply roofline of MI355X: 256 CUs x 4 SIMDs at 2.4 GHz, each SIMD
+# issuing one wave64 v_mad_u64_u32 (64 limb products of 32x32->64 bits) every
+# 4 cycles, i.e. 64 limb products per clock per CU.  (Simple 32-bit ALU ops
+# such as v_add_u32 issue twice as fast on gfx950; the probe mode measures both.)
+PEAK_LIMB_PRODUCTS = 256 * 4 * 16 * 2.4e9
 
 
 def prec_rows(x):
@@ -69,6 +71,35 @@ def cpu_baseline(c, q_gpu, r_gpu, budget_s=10.0):
             "sample": f"first {n} of {len(u)} instances of {c['name']} (Knuth D, gcc -O2, OpenMP)"}, exact, n
 
 
+PROBES = ["v_mad_u64_u32", "v_mad_u64_u32+v_addc_co_u32", "v_mul_lo_u32+v_mul_hi_u32", "v_add_u32",
+          "v_mul_u32_u24"]
+
+
+def probe_rates():
+    """Measured issue rates of the candidate limb-product instructions (one
+    JSON line): lane-operations/s over all CUs and the implied cycles per wave64
+    instruction sequence per SIMD at the 2.4 GHz peak clock."""
+    import ctypes
+    import torch
+    from paper_2606_06386_amd import build as hb
+    L = ctypes.CDLL(hb.PROBE_LIB)
+    L.mp_probe_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)]
+    blocks, iters = 8192, 4000
+    scratch = torch.empty(blocks * 256, dtype=torch.int32, device="cuda:0")
+    out = {"probe": "integer issue rates", "blocks": blocks, "threads": 256, "iters": iters, "rates": {}}
+    for v, name in enumerate(PROBES):
+        ms, ops = ctypes.c_float(), ctypes.c_double()
+        for _ in range(3):
+            rc = L.mp_probe_rate(v, iters, blocks, ctypes.c_void_p(scratch.data_ptr()), ctypes.byref(ms),
+                                 ctypes.byref(ops))
+            assert rc == 0, rc
+        rate = ops.value / (ms.value * 1e-3)
+        cyc = 256 * 4 * 2.4e9 / (rate / 64)
+        out["rates"][name] = {"lane_ops_per_s": rate, "ms": ms.value, "cycles_per_wave_op_at_2p4GHz": cyc}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +107,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", action="store_true", help="measure integer instruction issue rates instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: every division instance is independent and this "
@@ -86,6 +118,9 @@ def main():
     from paper_2606_06386_amd import binding
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.probe:
+        probe_rates()
+        return
     dev = torch.device("cuda:0")
     c = workload(args.config)
     u_h, v_h, nq = c["u"], c["v"], c["nq"]

@@ -9,6 +9,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libmpdiv.so")
 SOURCES = [os.path.join(HERE, "csrc", "mpdiv.hip")]
+# instruction issue-rate probe (calibrates the integer-multiply roofline)
+PROBE_LIB = os.path.join(HERE, "libmpprobe.so")
+PROBE_SOURCES = [os.path.join(HERE, "csrc", "probe_rates.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("mp_prims_hip.hpp", "mp_core.hpp", "mp_div.hpp")]
 
 HIPCC_FLAGS = [
@@ -19,13 +22,18 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, *SOURCES]
+def _hipcc(out, sources, verbose):
+    tmp = out + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, *sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(LIB, SOURCES, verbose)
+    _hipcc(PROBE_LIB, PROBE_SOURCES, verbose)
     return LIB
 
 
