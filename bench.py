@@ -72,7 +72,8 @@ def cpu_baseline(c, q_gpu, r_gpu, budget_s=10.0):
 
 
 PROBES = ["v_mad_u64_u32", "v_mad_u64_u32+v_addc_co_u32", "v_mul_lo_u32+v_mul_hi_u32", "v_add_u32",
-          "v_mul_u32_u24"]
+          "v_mul_u32_u24", "v_addc_co_u32_e64", "v_addc_co_u32_e32", "v_add3_u32", "v_lshl_add_u64",
+          "v_cndmask_b32_e64", "v_mad_u64_u32+v_add_u32", "v_dot4_u32_u8", "v_mfma_i32_32x32x32_i8"]
 
 
 def probe_rates():
@@ -96,7 +97,10 @@ def probe_rates():
             assert rc == 0, rc
         rate = ops.value / (ms.value * 1e-3)
         cyc = 256 * 4 * 2.4e9 / (rate / 64)
-        out["rates"][name] = {"lane_ops_per_s": rate, "ms": ms.value, "cycles_per_wave_op_at_2p4GHz": cyc}
+        rec = {"lane_ops_per_s": rate, "ms": ms.value, "cycles_per_wave_op_at_2p4GHz": cyc}
+        if name.startswith("v_mfma"):   # 8 wave-level MFMAs per iteration, 32*32*32 int8 MACs each
+            rec = {"macs_per_s": rate / 64 * 32768, "ms": ms.value, "cycles_per_mfma_per_simd_at_2p4GHz": cyc}
+        out["rates"][name] = rec
     print(json.dumps(out), flush=True)
 
 

@@ -27,7 +27,7 @@ namespace mp {
 constexpr int kRCol = 4;                 // product columns per lane
 constexpr int kStrip = kLanes * kRCol;   // product columns per wave pass
 constexpr int kPad = kStrip + 8;         // zero guard on both sides of a staged window operand
-constexpr int kCMax = 16;                // most limbs one thread handles in a linear operation
+constexpr int kCMax = 17;                // most limbs one thread handles in a linear operation
 
 // control block at the start of the instance's LDS (32-bit words)
 constexpr int kCtlRed = 0;       // 16 per-wave reduction slots
@@ -169,19 +169,17 @@ MP_DEV int cmp(uint32_t *ctl, int n, const FX &x, const FY &y)
 // (generate, propagate) pairs are combined in LDS.  Inputs are read before
 // the internal barrier and outputs written after it, so out may overwrite
 // the storage x or y read from.
-template <int T, class FX, class FY, class FO>
-MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
-                       const FX &x, const FY &y, const FO &out)
+template <int T, int CM, class FX, class FY, class FO>
+MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin,
+                             const FX &x, const FY &y, const FO &out)
 {
     constexpr int W = T / kLanes;
-    sync();
-    const int C = (n + T - 1) / T;
     const int k0 = tid() * C;
-    uint32_t z[kCMax];
+    uint32_t z[CM];
     uint32_t c = 0;
     bool prop = true;
 #pragma unroll
-    for (int j = 0; j < kCMax; j++) {
+    for (int j = 0; j < CM; j++) {
         const int k = k0 + j;
         if (j < C && k < n) {
             const uint32_t a = x(k), b = y(k);
@@ -200,7 +198,7 @@ MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
     }
     const uint64_t G = ballot(c != 0), P = ballot(prop), X = G | P;
     const uint64_t s0 = X + G;
-    const int w = tid() / kLanes;
+    const int w = uniform(tid() / kLanes);
     if (lane() == 0) {
         ctl[kCtlScan + 2 * w] = s0 < X ? 1u : 0u;      // wave generates
         ctl[kCtlScan + 2 * w + 1] = (~P == 0) ? 1u : 0u;  // wave propagates
@@ -216,7 +214,7 @@ MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
     const uint64_t cm = (X + G + (uint64_t)cin_w) ^ X ^ G;
     uint32_t ci = (uint32_t)(cm >> lane()) & 1u;
 #pragma unroll
-    for (int j = 0; j < kCMax; j++) {
+    for (int j = 0; j < CM; j++) {
         const int k = k0 + j;
         if (j < C && k < n) {
             if (!sub) {
@@ -231,6 +229,19 @@ MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
         }
     }
     return cout;
+}
+
+template <int T, class FX, class FY, class FO>
+MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
+                       const FX &x, const FY &y, const FO &out)
+{
+    sync();
+    // odd chunk length: lanes then touch LDS with an odd word stride (no bank conflicts)
+    const int C = ((n + T - 1) / T) | 1;
+    if (C == 1) return addsub_chunk<T, 1>(ctl, n, C, sub, cin, x, y, out);
+    if (C == 3) return addsub_chunk<T, 3>(ctl, n, C, sub, cin, x, y, out);
+    if (C <= 7) return addsub_chunk<T, 7>(ctl, n, C, sub, cin, x, y, out);
+    return addsub_chunk<T, kCMax>(ctl, n, C, sub, cin, x, y, out);
 }
 
 // dst[k] = src(k) for k in [0, n), zero for k in [n, clear)
@@ -269,7 +280,7 @@ MP_DEV void mul(uint32_t *ctl, uint32_t *p, int ncols,
         return;
     }
     const int nstrips = (ncols + kStrip - 1) / kStrip;
-    const int w = tid() / kLanes, l = lane();
+    const int w = uniform(tid() / kLanes), l = lane();
     for (int s = w; s < nstrips; s += W) {
         const int K0 = s * kStrip, k0 = K0 + l * kRCol;
         const int ilo = imax(0, K0 - nb + 1) & ~3;
@@ -277,21 +288,45 @@ MP_DEV void mul(uint32_t *ctl, uint32_t *p, int ncols,
         uint64_t lo[4] = {0, 0, 0, 0};
         uint32_t hi[4] = {0, 0, 0, 0};
         if (ilo < ihi) {
-            Limb4 wh = load4(bw + (k0 - ilo));
-            for (int i = ilo; i < ihi; i += 4) {
-                const Limb4 wl = load4(bw + (k0 - i - 4));
-                uint32_t a0 = a[i], a1 = a[i + 1], a2 = a[i + 2], a3 = a[i + 3];
-                if (i + 4 > na) {   // last block: rows past the operand are zero
-                    a1 = i + 1 < na ? a1 : 0u;
-                    a2 = i + 2 < na ? a2 : 0u;
-                    a3 = 0u;
+            // column k0+r, row i+t takes window limb k0 + r - i - t; per block
+            // of rows i..i+3 the lane needs window limbs k0-i-3 .. k0-i+3
+            const uint32_t *wp = bw + (k0 - ilo);
+            const uint32_t *ap = a + ilo;
+            int nblk = (ihi - ilo) >> 2;
+            for (; nblk >= 2; nblk -= 2) {
+                const Limb4 w0 = load4(wp), w1 = load4(wp - 4), w2 = load4(wp - 8);
+                const uint32_t a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
+                const uint32_t a4 = ap[4], a5 = ap[5], a6 = ap[6], a7 = ap[7];
+                mac4(lo, hi, a0, w0.x, w0.y, w0.z, w0.w);
+                mac4(lo, hi, a1, w1.w, w0.x, w0.y, w0.z);
+                mac4(lo, hi, a2, w1.z, w1.w, w0.x, w0.y);
+                mac4(lo, hi, a3, w1.y, w1.z, w1.w, w0.x);
+                mac4(lo, hi, a4, w1.x, w1.y, w1.z, w1.w);
+                mac4(lo, hi, a5, w2.w, w1.x, w1.y, w1.z);
+                mac4(lo, hi, a6, w2.z, w2.w, w1.x, w1.y);
+                mac4(lo, hi, a7, w2.y, w2.z, w2.w, w1.x);
+                keep(w2.x);   // keeps the third window load one aligned 16-byte read
+                wp -= 8;
+                ap += 8;
+            }
+            const int rem = (ihi - ilo) - ((ihi - ilo) & ~7);   // rows left: 0..7
+            if (rem > 0) {
+                // last rows: those at or past ihi (<= na) read as zero
+                const int i = ihi - rem;
+                const Limb4 w0 = load4(wp), w1 = load4(wp - 4), w2 = load4(wp - 8);
+                const uint32_t a0 = ap[0];
+                const uint32_t a1 = i + 1 < ihi ? ap[1] : 0u, a2 = i + 2 < ihi ? ap[2] : 0u;
+                const uint32_t a3 = i + 3 < ihi ? ap[3] : 0u, a4 = i + 4 < ihi ? ap[4] : 0u;
+                const uint32_t a5 = i + 5 < ihi ? ap[5] : 0u, a6 = i + 6 < ihi ? ap[6] : 0u;
+                mac4(lo, hi, a0, w0.x, w0.y, w0.z, w0.w);
+                mac4(lo, hi, a1, w1.w, w0.x, w0.y, w0.z);
+                mac4(lo, hi, a2, w1.z, w1.w, w0.x, w0.y);
+                mac4(lo, hi, a3, w1.y, w1.z, w1.w, w0.x);
+                if (rem > 4) {
+                    mac4(lo, hi, a4, w1.x, w1.y, w1.z, w1.w);
+                    mac4(lo, hi, a5, w2.w, w1.x, w1.y, w1.z);
+                    mac4(lo, hi, a6, w2.z, w2.w, w1.x, w1.y);
                 }
-                // column k0+r, row i+t takes window limb k0 + r - i - t
-                mac4(lo, hi, a0, wh.x, wh.y, wh.z, wh.w);
-                mac4(lo, hi, a1, wl.w, wh.x, wh.y, wh.z);
-                mac4(lo, hi, a2, wl.z, wl.w, wh.x, wh.y);
-                mac4(lo, hi, a3, wl.y, wl.z, wl.w, wh.x);
-                wh = wl;
             }
         }
         // lane-local carry: z = column sums as limbs, c = carry into column k0+4

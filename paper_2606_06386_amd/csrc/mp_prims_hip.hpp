@@ -57,20 +57,23 @@ MP_DEV void mac4(uint64_t (&lo)[4], uint32_t (&hi)[4], uint32_t a,
         : "v"(a), "v"(b0), "v"(b1), "v"(b2), "v"(b3));
 }
 
-// 16-byte LDS/global vector load and store of four limbs
+// marks a value as used without emitting any instruction
+MP_DEV void keep(uint32_t x) { asm volatile("" : : "v"(x)); }
+
+// 16-byte vector load and store of four limbs; p must be 16-byte aligned
 struct Limb4 {
     uint32_t x, y, z, w;
 };
 
 MP_DEV Limb4 load4(const uint32_t *p)
 {
-    uint4 v = *reinterpret_cast<const uint4 *>(p);
+    const uint4 v = *reinterpret_cast<const uint4 *>(__builtin_assume_aligned(p, 16));
     return Limb4{v.x, v.y, v.z, v.w};
 }
 
 MP_DEV void store4(uint32_t *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d)
 {
-    *reinterpret_cast<uint4 *>(p) = make_uint4(a, b, c, d);
+    *reinterpret_cast<uint4 *>(__builtin_assume_aligned(p, 16)) = make_uint4(a, b, c, d);
 }
 
 }  // namespace mp
