@@ -53,6 +53,20 @@ def limb_products(u, v):
     return total
 
 
+def measured_traffic(workload_name):
+    """HBM bytes per launch of k_divrem from committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE counts (each scaled by what the counter reads for a 256 MiB
+    device copy), or None when those counts were taken on other kernel sources
+    or another workload."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_divrem_{workload_name.split('_', 1)[1]}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in rec["sources"])).hexdigest()
+    return rec["traffic_bytes_per_dispatch"] if h == rec["source_sha256"] else None
+
+
 def cpu_baseline(c, q_gpu, r_gpu, budget_s=10.0):
     """The oracle (plain C, OpenMP over instances) on a bounded sample of the
     same workload; also checks the GPU results of the sample bit-exactly."""
@@ -157,6 +171,7 @@ def main():
     q_h, r_h = q.cpu().numpy().view(np.uint32), r.cpu().numpy().view(np.uint32)
     W = limb_products(u_h, v_h)
     achieved = W / (kmean * 1e-3)
+    algo_bytes = 4 * (u_h.size + v_h.size + q_h.size + r_h.size) + 4 * batch   # u, v in; q, r, status out
     line = {
         "metric": METRIC,
         "value": batch * args.steps / elapsed,
@@ -175,8 +190,9 @@ def main():
         "kernel_ms": {"mean": kmean, "median": kernel_ms[len(kernel_ms) // 2], "min": kernel_ms[0]},
         "limb_products_per_launch": W,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LIMB_PRODUCTS / 1e12,
-                     "unit": "T limb-products/s", "frac": achieved / PEAK_LIMB_PRODUCTS, "traffic": None,
-                     "kernel": "k_divrem"},
+                     "unit": "T limb-products/s", "frac": achieved / PEAK_LIMB_PRODUCTS,
+                     "traffic": measured_traffic(c["name"]), "traffic_unit": "bytes/launch",
+                     "algorithmic_bytes": algo_bytes, "kernel": "k_divrem"},
         "status_ok": int((status == 0).sum()),
     }
     if not args.no_cpu_baseline:

@@ -30,12 +30,13 @@ constexpr int kPad = kStrip + 8;         // zero guard on both sides of a staged
 constexpr int kCMax = 17;                // most limbs one thread handles in a linear operation
 
 // control block at the start of the instance's LDS (32-bit words)
-constexpr int kCtlRed = 0;       // 16 per-wave reduction slots
-constexpr int kCtlScan = 16;     // 16 x (generate, propagate) wave summaries
-constexpr int kCtlBcast = 48;    // 16 broadcast scalars
-constexpr int kCtlStrip = 64;    // 2 words per strip carry, up to 96 strips
+constexpr int kCtlRed = 0;       // 3 x 16 per-wave reduction slots
+constexpr int kCtlScan = 48;     // 16 x (generate, propagate) wave summaries
+constexpr int kCtlPrec = 80;     // 16 per-wave result-precision slots of the last addsub
+constexpr int kCtlStrip = 96;    // 2 words per strip carry, up to 72 strips
+constexpr int kCtlBcast = 240;   // 16 broadcast scalars
 constexpr int kCtlWords = 256;
-constexpr int kMaxStrips = 96;
+constexpr int kMaxStrips = 72;
 
 MP_DEV int round4(int x) { return (x + 3) & ~3; }
 MP_DEV int imin(int a, int b) { return a < b ? a : b; }
@@ -59,6 +60,12 @@ struct Span {
 
 struct Zero {
     MP_DEV uint32_t operator()(int) const { return 0u; }
+};
+
+// a one-limb number x
+struct Limb0 {
+    uint32_t x;
+    MP_DEV uint32_t operator()(int k) const { return k == 0 ? x : 0u; }
 };
 
 // B^e
@@ -124,6 +131,30 @@ MP_DEV uint32_t wg_max(uint32_t *ctl, uint32_t x)
     return uniform(r);
 }
 
+// element-wise maxima of N values per thread over the workgroup (N <= 3)
+template <int T, int N>
+MP_DEV void wg_max_n(uint32_t *ctl, uint32_t (&x)[N])
+{
+    constexpr int W = T / kLanes;
+    const int w = uniform(tid() / kLanes);
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        const uint32_t m = wave_max(x[i]);
+        if (lane() == 0) ctl[kCtlRed + 16 * i + w] = m;
+    }
+    sync();
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        uint32_t r = 0;
+#pragma unroll
+        for (int v = 0; v < W; v++) {
+            const uint32_t y = ctl[kCtlRed + 16 * i + v];
+            r = r > y ? r : y;
+        }
+        x[i] = uniform(r);
+    }
+}
+
 // max over k in [0, n) of f(k)  (f(k) >= 0)
 template <int T, class F>
 MP_DEV int reduce_max(uint32_t *ctl, int n, const F &f)
@@ -168,7 +199,8 @@ MP_DEV int cmp(uint32_t *ctl, int n, const FX &x, const FY &y)
 // c_{i+1} = g_i | (p_i & c_i)); across the <= 16 waves the per-wave
 // (generate, propagate) pairs are combined in LDS.  Inputs are read before
 // the internal barrier and outputs written after it, so out may overwrite
-// the storage x or y read from.
+// the storage x or y read from.  The precision of z (1 + index of its top
+// nonzero limb, 0 for zero) is left in per-wave slots for read_prec.
 template <int T, int CM, class FX, class FY, class FO>
 MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin,
                              const FX &x, const FY &y, const FO &out)
@@ -213,6 +245,7 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
     }
     const uint64_t cm = (X + G + (uint64_t)cin_w) ^ X ^ G;
     uint32_t ci = (uint32_t)(cm >> lane()) & 1u;
+    uint32_t top = 0;
 #pragma unroll
     for (int j = 0; j < CM; j++) {
         const int k = k0 + j;
@@ -226,9 +259,31 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
                 ci &= (o == 0u) ? 1u : 0u;
             }
             out(k, z[j]);
+            top = z[j] ? (uint32_t)(k + 1) : top;
         }
     }
+    // chunks ascend with the lane, so the wave's top is the top of its highest nonzero lane
+    const uint64_t nzl = ballot(top != 0);
+    const uint32_t wtop = nzl ? readlane(top, 63 - __builtin_clzll(nzl)) : 0u;
+    if (lane() == 0) ctl[kCtlPrec + w] = wtop;
     return cout;
+}
+
+// precision of the result of the last addsub (reads the per-wave slots after a
+// barrier); `off` converts to the coordinates of a Store with that offset
+template <int T>
+MP_DEV int read_prec(uint32_t *ctl, int off = 0)
+{
+    constexpr int W = T / kLanes;
+    sync();
+    uint32_t r = 0;
+#pragma unroll
+    for (int v = 0; v < W; v++) {
+        const uint32_t y = ctl[kCtlPrec + v];
+        r = r > y ? r : y;
+    }
+    const int p = (int)uniform(r) - off;
+    return p > 0 ? p : 0;
 }
 
 template <int T, class FX, class FY, class FO>
@@ -256,7 +311,7 @@ MP_DEV void copy(uint32_t *dst, int n, int clear, const FS &src)
 // ------------------------------------------------------------- multiply
 
 // p[0, ncols) = (a * b) mod B^ncols, ncols <= na + nb (ncols = na + nb is the
-// full product).  `a` (na limbs, any LDS position, readable up to 3 limbs past
+// full product); returns the precision of the result.  `a` (na limbs, any LDS position, readable up to 3 limbs past
 // its end) is the row operand, read with wave-uniform addresses; `bw` points
 // at limb 0 of the window operand (nb limbs) staged in LDS with kPad zero
 // limbs on both sides, 16-byte aligned.  The shorter operand should be the
@@ -270,14 +325,14 @@ MP_DEV void copy(uint32_t *dst, int n, int clear, const FS &src)
 // in-wave (lane-local carry, neighbour carry by shuffle, lookahead by
 // ballot); the carry leaving each strip is added by one final addsub pass.
 template <int T>
-MP_DEV void mul(uint32_t *ctl, uint32_t *p, int ncols,
-                const uint32_t *a, int na, const uint32_t *bw, int nb)
+MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
+               const uint32_t *a, int na, const uint32_t *bw, int nb)
 {
     constexpr int W = T / kLanes;
     sync();
     if (na == 0 || nb == 0 || ncols <= 0) {
         for (int k = tid(); k < ncols; k += T) p[k] = 0u;
-        return;
+        return 0;
     }
     const int nstrips = (ncols + kStrip - 1) / kStrip;
     const int w = uniform(tid() / kLanes), l = lane();
@@ -375,6 +430,7 @@ MP_DEV void mul(uint32_t *ctl, uint32_t *p, int ncols,
     // add the strip carries; the product fits ncols limbs (or is taken mod B^ncols)
     addsub<T>(ctl, ncols, false, 0u, Span{p, 0, ncols}, StripCarries{ctl + kCtlStrip, nstrips},
               Store{p, 0, ncols});
+    return read_prec<T>(ctl);
 }
 
 // --------------------------------------------------------- short division

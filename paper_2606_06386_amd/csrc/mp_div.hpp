@@ -82,16 +82,17 @@ MP_HD int mul_lds_words(int na, int nb)
 
 // ------------------------------------------------------------------ helpers
 
-// p[0, ncols) = x*y mod B^ncols: the longer operand is staged as the window
+// p[0, ncols) = x*y mod B^ncols: the longer operand is staged as the window;
+// returns the precision of the result
 template <int T>
-MP_DEV void product(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *x, int nx,
-                    const uint32_t *y, int ny, uint32_t *sb, int &sbext)
+MP_DEV int product(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *x, int nx,
+                   const uint32_t *y, int ny, uint32_t *sb, int &sbext)
 {
     const uint32_t *rows = nx >= ny ? y : x, *win = nx >= ny ? x : y;
     const int nr = nx >= ny ? ny : nx, nwin = nx >= ny ? nx : ny;
     copy<T>(sb, nwin, sbext, Span{win, 0, nwin});
     sbext = nwin;
-    mul<T>(ctl, p, ncols, rows, nr, sb, nwin);
+    return mul<T>(ctl, p, ncols, rows, nr, sb, nwin);
 }
 
 // dst[0, n) = src limbs [0, e) zero-padded, where e = prec(src) must be <= n;
@@ -122,11 +123,11 @@ MP_DEV int ceil_log2(int x)   // x >= 1
 
 // Initial approximation and the Refine loop for B^k <= v < B^(k+1), k >= 1,
 // h - k >= 1, B < v <= B^h / 2, v not a power of B.  v is in V (k+1 limbs).
-// On return the shifted inverse is the limbs of W above `shf`, with W's
-// nonzero limbs inside [0, we).  Returns false if a capacity guard trips or
-// a Step result turns negative (never expected).
+// On return the shifted inverse is the limbs of W above `shf`; W's nonzero
+// limbs lie inside [0, we) and nw = prec(W).  Returns false if a capacity
+// guard trips or a Step result turns negative (never expected).
 template <int T>
-MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, int &we, int &shf,
+MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, int &we, int &nw, int &shf,
                    int &sbext)
 {
     uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
@@ -142,7 +143,10 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
         W[2] = (uint32_t)w0;
         W[3] = (uint32_t)(w0 >> 32);
         W[4] = (uint32_t)(w0 >> 64);
+        ctl[kCtlBcast + 1] = W[4] ? 5u : W[3] ? 4u : 3u;
     }
+    sync();
+    nw = (int)uniform(ctl[kCtlBcast + 1]);
     we = 5;
     int l = 2;
     const int iters = 2 + (d - 1 <= 1 ? 0 : ceil_log2(d - 1));
@@ -153,44 +157,39 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
         const uint32_t *vp = V + s;          // divisor prefix shift_{-s}(v)
         const int nvp = k + 1 - s;
         const int hp = H - m, lp = l - g;   // PowDiff(v', w, H - m, l - g)
-        const int nw = prec<T>(ctl, we, Span{W, 0, we});
         const int L = nvp + nw - lp + 1;
         bool sign;
-        int nxb;
+        int nx;
         if (L >= hp) {                      // full product, compare with B^hp
             const int np0 = nvp + nw;
             if (np0 > pl.capP) return false;
-            product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext);
-            const int np = prec<T>(ctl, np0, Span{P, 0, np0});
+            const int np = product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext);
             if (np <= hp) {                 // P < B^hp: x = B^hp - P
                 if (hp > pl.capX) return false;
                 sign = true;
-                nxb = hp;
                 addsub<T>(ctl, hp, true, 0u, Zero{}, Span{P, 0, np}, Store{X, 0, hp});
             } else {                        // x = P - B^hp
                 if (np > pl.capX) return false;
                 sign = false;
-                nxb = np;
                 addsub<T>(ctl, np, true, 0u, Span{P, 0, np}, PowB{hp}, Store{X, 0, np});
             }
+            nx = read_prec<T>(ctl);
         } else {                            // close product: P = v'w mod B^L
             if (L > pl.capP || L > pl.capX) return false;
-            product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext);
-            const int np = prec<T>(ctl, L, Span{P, 0, L});
+            const int np = product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext);
             if (np == 0) {                  // v'w = B^hp exactly
                 sign = true;
-                nxb = 0;
+                nx = 0;
             } else if (np < L) {            // top limb 0: v'w = B^hp + P
                 sign = false;
-                nxb = np;
+                nx = np;
                 copy<T>(X, np, 0, Span{P, 0, np});
             } else {                        // v'w = B^hp - (B^L - P)
                 sign = true;
-                nxb = L;
                 addsub<T>(ctl, L, true, 0u, Zero{}, Span{P, 0, L}, Store{X, 0, L});
+                nx = read_prec<T>(ctl);
             }
         }
-        const int nx = nxb ? prec<T>(ctl, nxb, Span{X, 0, nxb}) : 0;
         // Step: res = shift_m(w) +- shift_{2m-H}(w x); then w = shift_{-post}(res)
         const int sh = H - 2 * m;
         const int post = i < 2 ? m : 1;
@@ -211,6 +210,7 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
                                       Store{W, post, pl.capW});
         if (!sign && co) return false;
         we = nres - post;
+        nw = read_prec<T>(ctl, post);
         if (i >= 2) l = l + m - 1;
     }
     shf = d < 2 ? 4 - d : 2;
@@ -279,14 +279,14 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
         copy<T>(V, k + 1, 0, Vg);
         copy<T>(W, 0, pl.capW, Zero{});
         copy<T>(SB - kPad, 0, pl.capSB + 2 * kPad, Zero{});
-        int we = 0, shf = 0, sbext = 0;
-        if (!refine<T>(ctl, pl, lds, h, k, we, shf, sbext)) {
+        int we = 0, nwi = 0, shf = 0, sbext = 0;
+        if (!refine<T>(ctl, pl, lds, h, k, we, nwi, shf, sbext)) {
             st = kInstInternal;
         } else {
             // exact fix-up: D = B^h - v*s with s within one of floor(B^h/v)
             uint32_t *S = W + shf;
             int se = imax(we - shf, 0);
-            const int ns = prec<T>(ctl, se, Span{S, 0, se});
+            const int ns = imax(nwi - shf, 0);
             const int d = h - k;
             int adj = 0;
             if (d >= 3) {
@@ -337,8 +337,18 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     const Span Ug{u, 0, nu}, Vg{v, 0, nv};
     int32_t st = kInstOk;
     bool ok = true;
-    const int h = prec<T>(ctl, nu, Ug);
-    const int nvv = prec<T>(ctl, nv, Vg);
+    // one pass over u and v: prec(u), prec(v), and the lowest nonzero limb of v
+    uint32_t red[3] = {0u, 0u, 0u};
+    sync();
+    for (int i = tid(); i < (nu > nv ? nu : nv); i += T) {
+        if (i < nu && u[i]) red[0] = (uint32_t)(i + 1);
+        if (i < nv && v[i]) {
+            red[1] = (uint32_t)(i + 1);
+            red[2] = red[2] ? red[2] : (uint32_t)(nv - i);
+        }
+    }
+    wg_max_n<T, 3>(ctl, red);
+    const int h = (int)red[0], nvv = (int)red[1], vlow = nv - (int)red[2];
     if (nvv == 0) {
         store_zero<T>(q, nq);
         store_zero<T>(r, nv);
@@ -353,8 +363,8 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         if (status && tid() == 0) *status = kInstOk;
         return;
     }
-    const int lowz = k > 0 && prec<T>(ctl, k, Vg) == 0;
     const uint32_t vk = v[k];
+    const bool lowz = vlow == k;                  // v = v_k B^k
     if (k == 0) {                                 // single-limb divisor: short division of u
         uint32_t *scratch = lds + kCtlWords, *Q = scratch + 2 * T;
         const uint32_t rem = shortdiv<T>(ctl, scratch, h, Ug, vk, Store{Q, 0, h});
@@ -367,54 +377,62 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
             for (int i = tid(); i < nv; i += T) r[i] = i < k ? u[i] : 0u;
     } else {
         const Plan pl = plan_div(h, k);
-        uint32_t *V = lds + pl.offV, *W = lds + pl.offW;
+        uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
         uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP;
-        copy<T>(V, k + 1, 0, Vg);
-        copy<T>(W, 0, pl.capW, Zero{});
-        copy<T>(SB - kPad, 0, pl.capSB + 2 * kPad, Zero{});
-        int we = 0, shf = 0, sbext = 0;
+        // V = v; W and the window staging area (with its guards) = 0
+        for (int i = tid(); i < pl.offP - pl.offV; i += T) {
+            const int o = pl.offV + i;
+            V[i] = o < pl.offW ? (i <= k ? v[i] : 0u) : 0u;
+        }
+        int we = 0, nw = 0, shf = 0, sbext = 0;
         bool good = true;
         if (k == h - 1 && (vk > 0x80000000u || (vk == 0x80000000u && !lowz))) {
             sync();                               // 2v > B^h: shinv = 1
             if (tid() == 0) W[0] = 1u;
             we = 1;
+            nw = 1;
             shf = 0;
         } else {
-            good = refine<T>(ctl, pl, lds, h, k, we, shf, sbext);
+            good = refine<T>(ctl, pl, lds, h, k, we, nw, shf, sbext);
         }
         if (good) {
             // q0 = shift_{-h}(u * s)
             const uint32_t *S = W + shf;
-            const int se = imax(we - shf, 0);
-            const int ns = prec<T>(ctl, se, Span{S, 0, se});
+            const int ns = imax(nw - shf, 0);
             good = ns <= h;
             if (good) {
                 copy<T>(SB, h, sbext, Ug);
                 sbext = h;
-                mul<T>(ctl, P, h + ns, S, ns, SB, h);
-                copy<T>(W, ns, we, Span{P, -h, h + ns});
-                we = ns;
-                const int nq0 = prec<T>(ctl, we, Span{W, 0, we});
-                // m = v * q0
+                const int np = mul<T>(ctl, P, h + ns, S, ns, SB, h);
+                const int nq0 = imax(np - h, 0);
+                copy<T>(W, nq0, we, Span{P, -h, h + ns});
+                we = nq0;
+                // m = v * q0;  r = u - m, corrected by whole multiples of v
                 const int ml = nq0 + k + 1;
                 product<T>(ctl, P, ml, W, nq0, V, k + 1, SB, sbext);
                 const int nc = imax(h, ml);
-                if (cmp<T>(ctl, nc, Ug, Span{P, 0, ml}) < 0) {        // u < m: q0 - 1, m - v
-                    const uint32_t b = addsub<T>(ctl, we, true, 1u, Span{W, 0, we}, Zero{}, Store{W, 0, we});
-                    addsub<T>(ctl, ml, true, 0u, Span{P, 0, ml}, Span{V, 0, k + 1}, Store{P, 0, ml});
-                    good = b == 0u;
+                uint32_t *R = SB, *R2 = X;
+                int delta = 0;
+                if (addsub<T>(ctl, nc, true, 0u, Ug, Span{P, 0, ml}, Store{R, 0, nc})) {
+                    // u < m (q0 one too large): r = u - m + v, the carry cancels the borrow
+                    good = addsub<T>(ctl, nc, false, 0u, Span{R, 0, nc}, Span{V, 0, k + 1}, Store{R, 0, nc}) == 1u;
+                    delta = -1;
                 }
-                // r = u - m (no borrow over all limbs of both: r <= u < B^h),
-                // then up to two upward corrections
-                uint32_t *R = SB;
-                const uint32_t bo = addsub<T>(ctl, nc, true, 0u, Ug, Span{P, 0, ml}, Store{R, 0, h});
-                good = good && bo == 0u;
+                // now 0 <= r < 3v < B^(k+2): at most two subtractions of v
+                const int rl = k + 2;
                 for (int it = 0; it < 3 && good; it++) {
-                    if (cmp<T>(ctl, h, Span{R, 0, h}, Span{V, 0, k + 1}) < 0) break;
+                    if (addsub<T>(ctl, rl, true, 0u, Span{R, 0, rl}, Span{V, 0, k + 1}, Store{R2, 0, rl}))
+                        break;                    // r < v
                     if (it == 2) { good = false; break; }
-                    addsub<T>(ctl, we + 1, false, 1u, Span{W, 0, we}, Zero{}, Store{W, 0, we + 1});
+                    uint32_t *t = R;
+                    R = R2;
+                    R2 = t;
+                    delta += 1;
+                }
+                if (good && delta != 0) {
+                    addsub<T>(ctl, we + 1, delta < 0, 0u, Span{W, 0, we}, Limb0{(uint32_t)(delta < 0 ? -delta : delta)},
+                              Store{W, 0, we + 1});
                     we += 1;
-                    addsub<T>(ctl, h, true, 0u, Span{R, 0, h}, Span{V, 0, k + 1}, Store{R, 0, h});
                 }
                 if (good) {
                     ok = store_fit<T>(ctl, q, nq, we, Span{W, 0, we});

@@ -29,6 +29,9 @@ MP_DEV uint32_t shfl_up1(uint32_t x)
 
 MP_DEV uint32_t shfl_xor(uint32_t x, int m) { return __shfl_xor(x, m); }
 
+// value of x in lane l (l wave-uniform)
+MP_DEV uint32_t readlane(uint32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
+
 // a value every lane of the wave already agrees on, moved to a scalar register
 MP_DEV uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 MP_DEV int uniform(int x) { return (int)__builtin_amdgcn_readfirstlane((uint32_t)x); }
