@@ -310,8 +310,79 @@ MP_DEV void copy(uint32_t *dst, int n, int clear, const FS &src)
 
 // ------------------------------------------------------------- multiply
 
-// p[0, ncols) = (a * b) mod B^ncols, ncols <= na + nb (ncols = na + nb is the
-// full product); returns the precision of the result.  `a` (na limbs, any LDS position, readable up to 3 limbs past
+// Turns the 96-bit column sums lo/hi of strip s (first column K0; lane l
+// holds columns K0 + 4l .. K0 + 4l + 3) into limbs: lane-local carry, the
+// neighbour's carry by shuffle, then a carry-lookahead over the wave from
+// ballots.  The limbs below ncols go to p; the carry leaving the strip goes to
+// the strip carry slot s (added to the next strip by the final addsub).
+MP_DEV void strip_resolve(uint32_t *ctl, int s, int K0, const uint64_t (&lo)[4], const uint32_t (&hi)[4],
+                          uint32_t *p, int ncols)
+{
+    const int l = lane();
+    const int k0 = K0 + l * kRCol;
+    // lane-local carry: z = column sums as limbs, c = carry into column k0+4
+    uint32_t z[4];
+    uint64_t c = 0;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const uint64_t t = lo[r] + c;
+        const uint32_t kap = t < c ? 1u : 0u;
+        z[r] = (uint32_t)t;
+        c = ((uint64_t)(hi[r] + kap) << 32) | (t >> 32);
+    }
+    // add the carry of the lane below (< 2^46), leaving a 1-bit carry g
+    const uint64_t cp = ((uint64_t)shfl_up1((uint32_t)(c >> 32)) << 32) | shfl_up1((uint32_t)c);
+    uint64_t acc = (uint64_t)z[0] + (uint32_t)cp;
+    z[0] = (uint32_t)acc;
+    acc = (acc >> 32) + (cp >> 32) + z[1];
+    z[1] = (uint32_t)acc;
+    acc = (acc >> 32) + z[2];
+    z[2] = (uint32_t)acc;
+    acc = (acc >> 32) + z[3];
+    z[3] = (uint32_t)acc;
+    const bool g = (acc >> 32) != 0;
+    const bool pr = (z[0] & z[1] & z[2] & z[3]) == 0xFFFFFFFFu;
+    const uint64_t G = ballot(g), P = ballot(pr), X = G | P;
+    const uint64_t sum = X + G;
+    uint32_t ci = (uint32_t)(((sum ^ X ^ G) >> l) & 1u);
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        z[r] += ci;
+        ci &= (z[r] == 0u) ? 1u : 0u;
+    }
+    if (k0 + 3 < ncols) {
+        store4(p + k0, z[0], z[1], z[2], z[3]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+            if (k0 + r < ncols) p[k0 + r] = z[r];
+    }
+    if (l == kLanes - 1) {
+        const uint64_t e = c + (sum < X ? 1u : 0u);
+        ctl[kCtlStrip + 2 * s] = (uint32_t)e;
+        ctl[kCtlStrip + 2 * s + 1] = (uint32_t)(e >> 32);
+    }
+}
+
+
+// p[c0, ncols) += the strip carries (strip s's carry enters at column
+// c0 + (s+1) kStrip), mod B^(ncols - c0); returns the precision as mul's
+template <int T>
+MP_DEV int add_strip_carries(uint32_t *ctl, uint32_t *p, int c0, int ncols, int nstrips)
+{
+    const int n = ncols - c0;
+    addsub<T>(ctl, n, false, 0u, Span{p + c0, 0, n}, StripCarries{ctl + kCtlStrip, nstrips}, Store{p + c0, 0, n});
+    const int e = read_prec<T>(ctl);
+    return e ? e + c0 : 0;
+}
+
+// p[c0, ncols) = the columns c0 .. ncols-1 of a * b, ncols <= na + nb (with
+// c0 = 0 and ncols = na + nb, the full product): every limb product of those
+// columns with all carries between them, and no carry from below c0, so
+// limbs [c0, ncols) hold floor(T / B^c0) mod B^(ncols-c0) for T = the sum of
+// the products in columns >= c0.  c0 is a multiple of 8; p below c0 is not
+// written.  Returns the precision of the result (c0 + the precision of the
+// stored limbs, or 0 when they are all zero).  `a` (na limbs, any LDS position, readable up to 3 limbs past
 // its end) is the row operand, read with wave-uniform addresses; `bw` points
 // at limb 0 of the window operand (nb limbs) staged in LDS with kPad zero
 // limbs on both sides, 16-byte aligned.  The shorter operand should be the
@@ -326,18 +397,18 @@ MP_DEV void copy(uint32_t *dst, int n, int clear, const FS &src)
 // ballot); the carry leaving each strip is added by one final addsub pass.
 template <int T>
 MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
-               const uint32_t *a, int na, const uint32_t *bw, int nb)
+               const uint32_t *a, int na, const uint32_t *bw, int nb, int c0 = 0)
 {
     constexpr int W = T / kLanes;
     sync();
-    if (na == 0 || nb == 0 || ncols <= 0) {
-        for (int k = tid(); k < ncols; k += T) p[k] = 0u;
+    if (na == 0 || nb == 0 || ncols <= c0) {
+        for (int k = c0 + tid(); k < ncols; k += T) p[k] = 0u;
         return 0;
     }
-    const int nstrips = (ncols + kStrip - 1) / kStrip;
+    const int nstrips = (ncols - c0 + kStrip - 1) / kStrip;
     const int w = uniform(tid() / kLanes), l = lane();
     for (int s = w; s < nstrips; s += W) {
-        const int K0 = s * kStrip, k0 = K0 + l * kRCol;
+        const int K0 = c0 + s * kStrip, k0 = K0 + l * kRCol;
         const int ilo = imax(0, K0 - nb + 1) & ~3;
         const int ihi = imin(na, imin(K0 + kStrip, ncols));
         uint64_t lo[4] = {0, 0, 0, 0};
@@ -384,53 +455,147 @@ MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
                 }
             }
         }
-        // lane-local carry: z = column sums as limbs, c = carry into column k0+4
-        uint32_t z[4];
-        uint64_t c = 0;
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const uint64_t t = lo[r] + c;
-            const uint32_t kap = t < c ? 1u : 0u;
-            z[r] = (uint32_t)t;
-            c = ((uint64_t)(hi[r] + kap) << 32) | (t >> 32);
-        }
-        // add the carry of the lane below (< 2^46), leaving a 1-bit carry g
-        const uint64_t cp = ((uint64_t)shfl_up1((uint32_t)(c >> 32)) << 32) | shfl_up1((uint32_t)c);
-        uint64_t acc = (uint64_t)z[0] + (uint32_t)cp;
-        z[0] = (uint32_t)acc;
-        acc = (acc >> 32) + (cp >> 32) + z[1];
-        z[1] = (uint32_t)acc;
-        acc = (acc >> 32) + z[2];
-        z[2] = (uint32_t)acc;
-        acc = (acc >> 32) + z[3];
-        z[3] = (uint32_t)acc;
-        const bool g = (acc >> 32) != 0;
-        const bool pr = (z[0] & z[1] & z[2] & z[3]) == 0xFFFFFFFFu;
-        const uint64_t G = ballot(g), P = ballot(pr), X = G | P;
-        const uint64_t sum = X + G;
-        uint32_t ci = (uint32_t)(((sum ^ X ^ G) >> l) & 1u);
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            z[r] += ci;
-            ci &= (z[r] == 0u) ? 1u : 0u;
-        }
-        if (k0 + 3 < ncols) {
-            store4(p + k0, z[0], z[1], z[2], z[3]);
-        } else {
-#pragma unroll
-            for (int r = 0; r < 4; r++)
-                if (k0 + r < ncols) p[k0 + r] = z[r];
-        }
-        if (l == kLanes - 1) {
-            const uint64_t e = c + (sum < X ? 1u : 0u);
-            ctl[kCtlStrip + 2 * s] = (uint32_t)e;
-            ctl[kCtlStrip + 2 * s + 1] = (uint32_t)(e >> 32);
-        }
+        strip_resolve(ctl, s, K0, lo, hi, p, ncols);
     }
-    // add the strip carries; the product fits ncols limbs (or is taken mod B^ncols)
-    addsub<T>(ctl, ncols, false, 0u, Span{p, 0, ncols}, StripCarries{ctl + kCtlStrip, nstrips},
-              Store{p, 0, ncols});
-    return read_prec<T>(ctl);
+    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips);
+}
+
+// ---------------------------------------------------- matrix-core product
+//
+// Exact products on the int8 matrix cores.  A number is rewritten in radix 256
+// with balanced digits in [-128, 127]:  x = sum d_i 256^i.  Adding 0x80 to
+// every byte and carrying (x + 0x8080...80) makes the carry into byte i exactly
+// [b_i + c_i >= 128], so the digit bytes are (x + 0x8080...80) XOR 0x8080...80
+// limb by limb, and the carry out of the top limb is one more digit (0 or 1).
+// For balanced digits the byte-column sums M_k = sum_{i+j=k} d_i e_j are exact
+// int32 values (|M_k| < 2^29 up to 8192-limb operands), and
+// x*y = sum_k M_k 256^k.
+//
+// Strip s of the product (limb columns 256s .. 256s+255 = byte columns
+// 1024s .. 1024s+1023) is one 32x32 matrix-core tile accumulated over the
+// diagonals d:  D[t][n] += sum_r X_d[t][r] Y_d[r][n]  with
+//   X_d[t][r] = e_(32d + t - r)            (Toeplitz slice of the short operand)
+//   Y_d[r][n] = d_(32(32s + n - d) + r)   (32 consecutive 32-byte blocks of the long one)
+// so D[t][n] = M_(32(32s + n) + t).  X is read from the byte-reversed digits of
+// the short operand (16 bytes per lane at any byte offset: 5 words and four
+// byte aligns); Y is one aligned 16-byte load per lane.  The accumulator of
+// lane (n, h) ends up holding the four byte sums of limb columns
+// 8n + 2q + h (q = 0..3) of the strip.
+
+// (limb k of x) + 0x80808080 for k < n: the radix-256 balancing addend
+struct Bal80 {
+    int n;
+    MP_DEV uint32_t operator()(int k) const { return k < n ? 0x80808080u : 0u; }
+};
+
+// balanced digit limbs in natural order: dst[k], k in [0, n]
+struct StoreBal {
+    uint32_t *p;
+    int n;
+    MP_DEV void operator()(int k, uint32_t z) const { p[k] = k < n ? z ^ 0x80808080u : z; }
+};
+
+// balanced digit limbs byte-reversed: dst[n - k] = bytes of limb k reversed
+struct StoreBalRev {
+    uint32_t *p;
+    int n;
+    MP_DEV void operator()(int k, uint32_t z) const { p[n - k] = bswap(k < n ? z ^ 0x80808080u : z); }
+};
+
+constexpr int kYPad = 248;   // zero limbs the long operand's digits need on each side (31 blocks)
+constexpr int kXPad = 16;    // zero words the reversed short operand needs on each side
+constexpr int kMfmaMin = 64; // shortest operand (limbs) for which the matrix-core product pays
+
+// Balanced digits of the long operand (ny limbs) into yb[0 .. ny] and of the
+// short operand (nx limbs) byte-reversed into xr[0 .. nx]; yb keeps kYPad zero
+// limbs below 0 and above its data (yb[ny+1 .. yclear) is cleared), xr gets
+// kXPad zero words on both sides.  The short operand must not live in xr's
+// padded range unless it is exactly the limbs the conversion reads first
+// (the reads all precede the writes inside addsub).
+template <int T, class FY, class FX>
+MP_DEV void mfma_operands(uint32_t *ctl, const FY &y, int ny, uint32_t *yb, int yclear,
+                          const FX &x, int nx, uint32_t *xr)
+{
+    sync();
+    for (int k = ny + 1 + tid(); k < yclear; k += T) yb[k] = 0u;
+    addsub<T>(ctl, ny + 1, false, 0u, y, Bal80{ny}, StoreBal{yb, ny});
+    addsub<T>(ctl, nx + 1, false, 0u, x, Bal80{nx}, StoreBalRev{xr, nx});
+    sync();
+    for (int k = tid(); k < 2 * kXPad; k += T) {
+        if (k < kXPad) xr[k - kXPad] = 0u;
+        else xr[nx + 1 + k - kXPad] = 0u;
+    }
+}
+
+// p[c0, ncols) = the columns c0 .. ncols-1 of x * y (as mul, c0 a multiple
+// of 8) from the digits prepared by mfma_operands (yb: ny+1 limbs of the long
+// operand, xr: nx+1 reversed limbs of the short); returns the precision of the
+// result.  With c0 > 0 the columns are those of the balanced radix-256 digit
+// products, T = sum of M_k 256^k over byte columns k >= 4 c0, which differs
+// from the limb-product sum by less than 2^16 c0 B^c0 in either direction.
+template <int T>
+MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, int ny,
+                    const uint32_t *xr, int nx, int c0 = 0)
+{
+    constexpr int W = T / kLanes;
+    sync();
+    if (ncols <= c0) return 0;
+    const int nstrips = (ncols - c0 + kStrip - 1) / kStrip;
+    const int w = uniform(tid() / kLanes), l = lane();
+    const int t = l & 31, h = l >> 5;
+    const int nyblk = (ny + 1 + 7) >> 3;          // 32-byte blocks of the long digits
+    const int R0 = 4 * (nx + 1) - 1;              // reversed byte x holds digit R0 - x
+    const int dmax = (4 * (nx + 1) + 30) >> 5;    // last diagonal touching the short digits
+    for (int s = w; s < nstrips; s += W) {
+        const int S0 = 32 * s + (c0 >> 3);        // first 8-limb block of the strip
+        const int dlo = imax(0, S0 - nyblk + 1), dhi = imin(dmax, S0 + 31);
+        MfmaAcc acc0 = mfma_zero(), acc1 = mfma_zero();
+        for (int d = dlo; d <= dhi; d += 2) {
+#pragma unroll
+            for (int e = 0; e < 2; e++) {
+                const int dd = d + e;
+                if (e == 1 && dd > dhi) break;
+                const int o = R0 - 32 * dd - t + 16 * h;   // first reversed byte of X_d row t, half h
+                const int wq = o >> 2;
+                const uint32_t sft = (uint32_t)o & 3u;
+                const uint32_t *xp = xr + wq;
+                const uint32_t q0 = xp[0], q1 = xp[1], q2 = xp[2], q3 = xp[3], q4 = xp[4];
+                const Limb4 yv = load4(yb + 8 * (S0 + t - dd) + 4 * h);
+                const uint32_t x0 = alignbyte(q1, q0, sft), x1 = alignbyte(q2, q1, sft);
+                const uint32_t x2 = alignbyte(q3, q2, sft), x3 = alignbyte(q4, q3, sft);
+                if (e == 0) acc0 = mfma_i8(acc0, x0, x1, x2, x3, yv.x, yv.y, yv.z, yv.w);
+                else acc1 = mfma_i8(acc1, x0, x1, x2, x3, yv.x, yv.y, yv.z, yv.w);
+            }
+        }
+        const MfmaAcc acc = mfma_add(acc0, acc1);
+        // limb columns 8t + 2q + h of the strip, biased to be non-negative: column c0
+        // gets 2^56, every other column 2^56 - 2^24 (the biases telescope to
+        // 2^24 B^ncols, i.e. to 0 mod B^ncols)
+        uint32_t tl[4], th[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int64_t m = (int64_t)mfma_get(acc, 4 * q) + (int64_t)mfma_get(acc, 4 * q + 1) * 256 +
+                              (int64_t)mfma_get(acc, 4 * q + 2) * 65536 + (int64_t)mfma_get(acc, 4 * q + 3) * 16777216;
+            const int col = s * kStrip + 8 * t + 2 * q + h;   // relative to c0
+            const uint64_t v = (uint64_t)(m + (col == 0 ? ((int64_t)1 << 56) : ((int64_t)1 << 56) - ((int64_t)1 << 24)));
+            tl[q] = (uint32_t)v;
+            th[q] = (uint32_t)(v >> 32);
+        }
+        // regroup: lane l takes columns 4l .. 4l+3; column 4l + j sits in lane
+        // (l >> 1) + 32 (j & 1), slot q = 2 (l & 1) + (j >> 1)
+        uint64_t lo[4];
+        const uint32_t hi[4] = {0u, 0u, 0u, 0u};
+        const int par = l & 1;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int src = (l >> 1) + 32 * (j & 1);
+            const uint32_t al = shfl(tl[j >> 1], src), ah = shfl(th[j >> 1], src);
+            const uint32_t bl = shfl(tl[2 + (j >> 1)], src), bh = shfl(th[2 + (j >> 1)], src);
+            lo[j] = par ? (((uint64_t)bh << 32) | bl) : (((uint64_t)ah << 32) | al);
+        }
+        strip_resolve(ctl, s, c0 + s * kStrip, lo, hi, p, ncols);
+    }
+    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips);
 }
 
 // --------------------------------------------------------- short division

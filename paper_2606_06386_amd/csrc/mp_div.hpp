@@ -36,10 +36,12 @@ MP_HD int hmax(int a, int b) { return a > b ? a : b; }
 // LDS layout of one division / shifted-inverse instance with h = prec(u)
 // (or the shinv precision) and k = prec(v) - 1, in 32-bit words.  Capacities
 // bound every intermediate of the method: w <= h-k+4 limbs, x <= k+8,
-// Refine products <= h+6, u*shinv <= 2h-k+1, shinv <= h-k+1.
+// Refine products <= h+6, u*shinv <= 2h-k+1, shinv <= h-k+1.  R holds the
+// reversed digits of the shorter operand of a matrix-core product (up to
+// h/2 + 15 limbs); the window area SB doubles as the long operand's digits.
 struct Plan {
-    int capV, capW, capX, capSB, capP;
-    int offV, offW, offX, offSB, offP;   // offSB: limb 0 of the staged window
+    int capV, capW, capX, capR, capSB, capP;
+    int offV, offW, offX, offR, offSB, offP;   // offR: word 0 of the reversed digits, offSB: limb 0 of the window
     int total;
 };
 
@@ -50,12 +52,14 @@ MP_HD Plan plan_div(int h, int k)
     p.capV = r4(k + 1);
     p.capW = r4(d + 8);
     p.capX = r4(k + 12);
+    p.capR = r4(h / 2 + 16);
     p.capSB = r4(hmax(hmax(h, k + 12), d + 8) + 4);
     p.capP = r4(hmax(2 * h - k + 1, h + 8) + 4);
     p.offV = kCtlWords;
     p.offW = p.offV + p.capV;
     p.offX = p.offW + p.capW;
-    p.offSB = p.offX + p.capX + kPad;
+    p.offR = p.offX + p.capX + kXPad;
+    p.offSB = p.offR + p.capR + kXPad + kPad;
     p.offP = p.offSB + p.capSB + kPad;
     p.total = p.offP + p.capP + 4;
     return p;
@@ -77,22 +81,40 @@ MP_HD int div_lds_words(int nu, int nv, int T)
 MP_HD int mul_lds_words(int na, int nb)
 {
     const int lo = na < nb ? na : nb, hi = na < nb ? nb : na;
-    return kCtlWords + r4(lo) + 4 + kPad + r4(hi) + kPad + r4(na + nb) + 4;
+    return kCtlWords + kXPad + r4(lo + 1) + kXPad + 4 + kPad + r4(hi + 1) + kPad + r4(na + nb) + 4;
 }
 
 // ------------------------------------------------------------------ helpers
 
-// p[0, ncols) = x*y mod B^ncols: the longer operand is staged as the window;
-// returns the precision of the result
+// p[c0, ncols) = columns c0 .. ncols-1 of x*y (c0 = 0: x*y mod B^ncols; see
+// mul and mul_mfma for c0 > 0, a multiple of 8); returns the precision of the
+// result.  Long enough products run on the matrix cores (long operand's
+// digits in sb, short operand's reversed digits in xr, which holds xrcap
+// limbs); the rest walk the rows on the VALU with the longer operand staged in
+// sb as window.
+template <int T, class FL, class FS>
+MP_DEV int product_views(uint32_t *ctl, uint32_t *p, int ncols, const FL &lng, int nl, const uint32_t *lng_lds,
+                         const FS &sht, int ns, const uint32_t *sht_lds, uint32_t *sb, int &sbext,
+                         uint32_t *xr, int xrcap, int c0 = 0)
+{
+    if (ns >= kMfmaMin && ns + 1 <= xrcap) {
+        mfma_operands<T>(ctl, lng, nl, sb, sbext, sht, ns, xr);
+        sbext = nl + 1;
+        return mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0);
+    }
+    copy<T>(sb, nl, sbext, lng);
+    sbext = nl;
+    return mul<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0);
+}
+
 template <int T>
 MP_DEV int product(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *x, int nx,
-                   const uint32_t *y, int ny, uint32_t *sb, int &sbext)
+                   const uint32_t *y, int ny, uint32_t *sb, int &sbext, uint32_t *xr, int xrcap, int c0 = 0)
 {
-    const uint32_t *rows = nx >= ny ? y : x, *win = nx >= ny ? x : y;
-    const int nr = nx >= ny ? ny : nx, nwin = nx >= ny ? nx : ny;
-    copy<T>(sb, nwin, sbext, Span{win, 0, nwin});
-    sbext = nwin;
-    return mul<T>(ctl, p, ncols, rows, nr, sb, nwin);
+    const uint32_t *sht = nx >= ny ? y : x, *lng = nx >= ny ? x : y;
+    const int ns = nx >= ny ? ny : nx, nl = nx >= ny ? nx : ny;
+    return product_views<T>(ctl, p, ncols, Span{lng, 0, nl}, nl, lng, Span{sht, 0, ns}, ns, sht, sb, sbext,
+                            xr, xrcap, c0);
 }
 
 // dst[0, n) = src limbs [0, e) zero-padded, where e = prec(src) must be <= n;
@@ -131,7 +153,7 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
                    int &sbext)
 {
     uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
-    uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP;
+    uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP, *XR = lds + pl.offR;
     const int g = 2, d = h - k;
     // w = shift_g(floor(B^3 / V)), V = v_{k-1} + v_k B; w0 <= B^2 has 3 limbs
     sync();
@@ -163,7 +185,7 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
         if (L >= hp) {                      // full product, compare with B^hp
             const int np0 = nvp + nw;
             if (np0 > pl.capP) return false;
-            const int np = product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext);
+            const int np = product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR);
             if (np <= hp) {                 // P < B^hp: x = B^hp - P
                 if (hp > pl.capX) return false;
                 sign = true;
@@ -176,7 +198,7 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
             nx = read_prec<T>(ctl);
         } else {                            // close product: P = v'w mod B^L
             if (L > pl.capP || L > pl.capX) return false;
-            const int np = product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext);
+            const int np = product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR);
             if (np == 0) {                  // v'w = B^hp exactly
                 sign = true;
                 nx = 0;
@@ -190,19 +212,29 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
                 nx = read_prec<T>(ctl);
             }
         }
-        // Step: res = shift_m(w) +- shift_{2m-H}(w x); then w = shift_{-post}(res)
+        // Step: res = shift_m(w) +- shift_{2m-H}(w x); then w = shift_{-post}(res).
+        // Only the columns of w x from cs = sh - 2 (rounded down to a multiple
+        // of 8) up are formed: the columns below change the shifted product by
+        // less than one unit of the iterate's last guard limb, and the sticky
+        // bit of the negative branch is taken from the formed columns below sh.
+        // The matrix-core digits can make the dropped part negative, so the
+        // formed sum T may exceed w x: one more column holds T < 2 B^(nw+nx),
+        // and nw + nx >= sh + 2 keeps T > 0 (w x >= B^(nw+nx-2) exceeds the
+        // dropped part).
         const int sh = H - 2 * m;
         const int post = i < 2 ? m : 1;
-        int nt = 0;
+        int nt = 0, cs = 0;
         if (nx) {
             nt = nw + nx;
+            cs = nt >= sh + 2 ? imax(sh - 2, 0) & ~7 : 0;
+            if (cs) nt += 1;
             if (nt > pl.capP) return false;
-            product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext);
+            product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, cs);
         }
         uint32_t sticky = 0;
-        if (!sign && nt > 0) {
+        if (!sign && nt > cs) {
             const int top = imin(sh, nt);
-            sticky = reduce_max<T>(ctl, top, [&](int j) -> uint32_t { return P[j] ? 1u : 0u; });
+            sticky = reduce_max<T>(ctl, top - cs, [&](int j) -> uint32_t { return P[cs + j] ? 1u : 0u; });
         }
         const int nres = imax(nw + m, nt - sh) + 1;
         if (nres - post > pl.capW) return false;
@@ -225,14 +257,22 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
 {
     uint32_t *ctl = lds;
     const int nlo = na < nb ? na : nb, nhi = na < nb ? nb : na;
-    const uint32_t *rows = na < nb ? a : b, *win = na < nb ? b : a;
-    uint32_t *A = lds + kCtlWords;
-    uint32_t *SBbase = A + r4(nlo) + 4;
-    uint32_t *SB = SBbase + kPad;
-    uint32_t *P = SB + r4(nhi) + kPad;
-    copy<T>(A, nlo, r4(nlo) + 4, Span{rows, 0, nlo});
-    copy<T>(SBbase, kPad + nhi, 2 * kPad + r4(nhi), Span{win, kPad, nhi});
-    mul<T>(ctl, P, na + nb, A, nlo, SB, nhi);
+    const uint32_t *sht = na < nb ? a : b, *lng = na < nb ? b : a;
+    uint32_t *A = lds + kCtlWords + kXPad;          // short operand (rows, or reversed digits)
+    uint32_t *SBbase = A + r4(nlo + 1) + kXPad + 4;
+    uint32_t *SB = SBbase + kPad;                   // long operand (window, or digits)
+    uint32_t *P = SB + r4(nhi + 1) + kPad;
+    int np;
+    if (nlo >= kMfmaMin) {
+        copy<T>(SBbase, 0, 2 * kPad + r4(nhi + 1), Zero{});
+        mfma_operands<T>(ctl, Span{lng, 0, nhi}, nhi, SB, 0, Span{sht, 0, nlo}, nlo, A);
+        np = mul_mfma<T>(ctl, P, na + nb, SB, nhi, A, nlo);
+    } else {
+        copy<T>(A, nlo, r4(nlo) + 4, Span{sht, 0, nlo});
+        copy<T>(SBbase, kPad + nhi, 2 * kPad + r4(nhi), Span{lng, kPad, nhi});
+        np = mul<T>(ctl, P, na + nb, A, nlo, SB, nhi);
+    }
+    (void)np;
     sync();
     for (int i = tid(); i < na + nb; i += T) c[i] = P[i];
 }
@@ -275,7 +315,7 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
     } else {
         const Plan pl = plan_div(h, k);
         uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
-        uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP;
+        uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP, *XR = lds + pl.offR;
         copy<T>(V, k + 1, 0, Vg);
         copy<T>(W, 0, pl.capW, Zero{});
         copy<T>(SB - kPad, 0, pl.capSB + 2 * kPad, Zero{});
@@ -283,41 +323,44 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
         if (!refine<T>(ctl, pl, lds, h, k, we, nwi, shf, sbext)) {
             st = kInstInternal;
         } else {
-            // exact fix-up: D = B^h - v*s with s within one of floor(B^h/v)
+            // exact fix-up: D = B^h - v s with s within two of floor(B^h/v), so
+            // -2v <= D < 3v.  D is formed as a signed Lr-limb number (Lr = k+3
+            // when h >= k+3: B^h vanishes mod B^Lr and |D| < B^Lr / 2), then
+            // moved into [0, v) by whole multiples of v.
             uint32_t *S = W + shf;
             int se = imax(we - shf, 0);
             const int ns = imax(nwi - shf, 0);
             const int d = h - k;
+            const int full = k + 1 + ns;
+            const int Lr = d >= 3 ? k + 3 : imax(full, h + 1) + 1;
+            const int pc = imin(Lr, full);
+            product<T>(ctl, P, pc, V, k + 1, S, ns, SB, sbext, XR, pl.capR);
+            addsub<T>(ctl, Lr, true, 0u, PowB{h}, Span{P, 0, pc}, Store{X, 0, Lr});
+            uint32_t *R = X, *R2 = P;
             int adj = 0;
-            if (d >= 3) {
-                const int L = k + 3;            // |D| < 2v < B^(k+2) and B^h = 0 mod B^L
-                product<T>(ctl, P, L, V, k + 1, S, ns, SB, sbext);
-                const int np = prec<T>(ctl, L, Span{P, 0, L});
+            bool good = true;
+            for (int it = 0; good; it++) {         // D < 0: s too large
                 sync();
-                const uint32_t top = P[L - 1];
-                if (np > 0 && top == 0u) {
-                    adj = -1;                   // D = -P < 0
-                } else if (np > 0) {            // D = B^L - P > 0
-                    addsub<T>(ctl, L, true, 0u, Zero{}, Span{P, 0, L}, Store{X, 0, L});
-                    if (cmp<T>(ctl, L, Span{X, 0, L}, Span{V, 0, k + 1}) >= 0) adj = 1;
-                }
-            } else {
-                const int np0 = k + 1 + ns;     // small inverse: full product
-                product<T>(ctl, P, np0, V, k + 1, S, ns, SB, sbext);
-                const int n = imax(np0, h + 1);
-                const int c = cmp<T>(ctl, n, Span{P, 0, np0}, PowB{h});
-                if (c > 0) {
-                    adj = -1;
-                } else if (c < 0) {
-                    addsub<T>(ctl, h, true, 0u, Zero{}, Span{P, 0, np0}, Store{X, 0, h});
-                    if (cmp<T>(ctl, h, Span{X, 0, h}, Span{V, 0, k + 1}) >= 0) adj = 1;
-                }
+                if (!(R[Lr - 1] >> 31)) break;
+                if (it == 4) { good = false; break; }
+                addsub<T>(ctl, Lr, false, 0u, Span{R, 0, Lr}, Span{V, 0, k + 1}, Store{R, 0, Lr});
+                adj -= 1;
             }
-            if (adj != 0) {
-                addsub<T>(ctl, se + 1, adj < 0, 1u, Span{S, 0, se}, Zero{}, Store{S, 0, se + 1});
+            for (int it = 0; good; it++) {         // D >= v: s too small
+                if (addsub<T>(ctl, Lr, true, 0u, Span{R, 0, Lr}, Span{V, 0, k + 1}, Store{R2, 0, Lr})) break;
+                if (it == 5) { good = false; break; }
+                uint32_t *t = R;
+                R = R2;
+                R2 = t;
+                adj += 1;
+            }
+            if (good && adj != 0) {
+                addsub<T>(ctl, se + 1, adj < 0, 0u, Span{S, 0, se}, Limb0{(uint32_t)(adj < 0 ? -adj : adj)},
+                          Store{S, 0, se + 1});
                 se += 1;
             }
-            ok = store_fit<T>(ctl, w, nw, se, Span{S, 0, se});
+            if (!good) st = kInstInternal;
+            if (good) ok = store_fit<T>(ctl, w, nw, se, Span{S, 0, se});
         }
     }
     if (st == kInstOk && !ok) st = kInstQWidth;
@@ -378,8 +421,8 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     } else {
         const Plan pl = plan_div(h, k);
         uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
-        uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP;
-        // V = v; W and the window staging area (with its guards) = 0
+        uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP, *XR = lds + pl.offR;
+        // V = v; W, X, R and the window staging area (with its guards) = 0
         for (int i = tid(); i < pl.offP - pl.offV; i += T) {
             const int o = pl.offV + i;
             V[i] = o < pl.offW ? (i <= k ? v[i] : 0u) : 0u;
@@ -401,29 +444,39 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
             const int ns = imax(nw - shf, 0);
             good = ns <= h;
             if (good) {
-                copy<T>(SB, h, sbext, Ug);
-                sbext = h;
-                const int np = mul<T>(ctl, P, h + ns, S, ns, SB, h);
+                // only the columns from c0 = h - 2 (rounded down to a multiple of 8)
+                // up: the products below c0 sum to less than B^h, so the top
+                // limbs are floor(u s / B^h) or one less (one more on the matrix
+                // cores, whose digit products below c0 may be negative)
+                const int c0 = imax(h - 2, 0) & ~7;
+                const int np = product_views<T>(ctl, P, h + ns, Ug, h, nullptr, Span{S, 0, ns}, ns, S, SB, sbext,
+                                                XR, pl.capR, c0);
                 const int nq0 = imax(np - h, 0);
                 copy<T>(W, nq0, we, Span{P, -h, h + ns});
                 we = nq0;
-                // m = v * q0;  r = u - m, corrected by whole multiples of v
-                const int ml = nq0 + k + 1;
-                product<T>(ctl, P, ml, W, nq0, V, k + 1, SB, sbext);
-                const int nc = imax(h, ml);
+                // With s within two of the shifted inverse (the Step products
+                // are clipped too), q - 4 <= q0 <= q + 3 and r0 = u - v q0 lies
+                // in [-3v, 5v): |r0| < B^(k+2) / 2, so r0 is exact as a signed
+                // (k+2)-limb number and only the low k+2 limbs of m = v q0 are
+                // needed.  The loops below allow one more step each way.
+                const int rl = k + 2;
+                product<T>(ctl, P, rl, W, nq0, V, k + 1, SB, sbext, XR, pl.capR);
                 uint32_t *R = SB, *R2 = X;
                 int delta = 0;
-                if (addsub<T>(ctl, nc, true, 0u, Ug, Span{P, 0, ml}, Store{R, 0, nc})) {
-                    // u < m (q0 one too large): r = u - m + v, the carry cancels the borrow
-                    good = addsub<T>(ctl, nc, false, 0u, Span{R, 0, nc}, Span{V, 0, k + 1}, Store{R, 0, nc}) == 1u;
-                    delta = -1;
+                addsub<T>(ctl, rl, true, 0u, Ug, Span{P, 0, rl}, Store{R, 0, rl});
+                // r0 < 0 (top bit of the signed value): add v until it is not
+                for (int it = 0; good; it++) {
+                    sync();
+                    if (!(R[rl - 1] >> 31)) break;
+                    if (it == 4) { good = false; break; }
+                    addsub<T>(ctl, rl, false, 0u, Span{R, 0, rl}, Span{V, 0, k + 1}, Store{R, 0, rl});
+                    delta -= 1;
                 }
-                // now 0 <= r < 3v < B^(k+2): at most two subtractions of v
-                const int rl = k + 2;
-                for (int it = 0; it < 3 && good; it++) {
+                // now 0 <= r < 6v
+                for (int it = 0; good; it++) {
                     if (addsub<T>(ctl, rl, true, 0u, Span{R, 0, rl}, Span{V, 0, k + 1}, Store{R2, 0, rl}))
                         break;                    // r < v
-                    if (it == 2) { good = false; break; }
+                    if (it == 5) { good = false; break; }
                     uint32_t *t = R;
                     R = R2;
                     R2 = t;

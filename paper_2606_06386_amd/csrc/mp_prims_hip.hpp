@@ -29,6 +29,9 @@ MP_DEV uint32_t shfl_up1(uint32_t x)
 
 MP_DEV uint32_t shfl_xor(uint32_t x, int m) { return __shfl_xor(x, m); }
 
+// value of x in lane src (src may differ per lane)
+MP_DEV uint32_t shfl(uint32_t x, int src) { return __shfl(x, src); }
+
 // value of x in lane l (l wave-uniform)
 MP_DEV uint32_t readlane(uint32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
 
@@ -59,6 +62,29 @@ MP_DEV void mac4(uint64_t (&lo)[4], uint32_t (&hi)[4], uint32_t a,
           "=&s"(c0), "=&s"(c1), "=&s"(c2), "=&s"(c3)
         : "v"(a), "v"(b0), "v"(b1), "v"(b2), "v"(b3));
 }
+
+// bytes [sel, sel + 4) of the 8-byte value hi:lo (sel in 0..3)
+MP_DEV uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t sel) { return __builtin_amdgcn_alignbyte(hi, lo, sel); }
+
+MP_DEV uint32_t bswap(uint32_t x) { return __builtin_bswap32(x); }
+
+// ---------------------------------------------------------- int8 matrix core
+// v_mfma_i32_32x32x32_i8: D[32x32] += X[32x32] * Y[32x32], int8 inputs, int32
+// sums.  Lane l supplies X row l%32 and Y column l%32, each as 16 bytes
+// (k = 16*(l/32) + byte index, the same k order for X and Y), and receives
+// D[8*(v/4) + 4*(l/32) + v%4][l%32] in accumulator element v.
+typedef int MfmaFrag __attribute__((ext_vector_type(4)));
+typedef int MfmaAcc __attribute__((ext_vector_type(16)));
+
+MP_DEV MfmaAcc mfma_zero() { return MfmaAcc{}; }
+MP_DEV MfmaAcc mfma_i8(MfmaAcc acc, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                       uint32_t y0, uint32_t y1, uint32_t y2, uint32_t y3)
+{
+    const MfmaFrag x = {(int)x0, (int)x1, (int)x2, (int)x3}, y = {(int)y0, (int)y1, (int)y2, (int)y3};
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(x, y, acc, 0, 0, 0);
+}
+MP_DEV int mfma_get(const MfmaAcc &acc, int v) { return acc[v]; }
+MP_DEV MfmaAcc mfma_add(MfmaAcc a, MfmaAcc b) { return a + b; }
 
 // marks a value as used without emitting any instruction
 MP_DEV void keep(uint32_t x) { asm volatile("" : : "v"(x)); }
