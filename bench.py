@@ -5,7 +5,16 @@ instance goes through shifted inverse, quotient product, remainder product
 and corrections).  Inputs are device-resident before the timed region.
 Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--config c2|c1|c3] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--config c2|c1|c3|c4] [--no-cpu-baseline]
+
+--config c5 runs the serving loop instead: 10^4 requests of 2^15..2^18 bits
+with Poisson arrivals at 10^3 .. 10^6 per second, continuous batching over
+mp_divrem_ragged; it reports throughput and p50/p99 latency per rate.
+
+--config c4 times the mixed-precision batch instead: 8192 divisions with
+dividends of 2^15..2^18 bits in one mp_divrem_ragged call (launch
+configuration from the autotuner), beside the same divisions as four
+uniform-width mp_divrem_batch launches.
 """
 import argparse
 import json
@@ -39,16 +48,31 @@ def workload(name):
     return {"c1": I.config_c1, "c2": I.config_c2, "c3": I.config_c3}[name]()
 
 
-def limb_products(u, v):
-    """Algorithmic limb products of one launch over the batch (cost model W)."""
+def limb_products(u, v, clipped=True):
+    """Algorithmic limb products of one launch over the batch: the cost model's
+    W_clipped (what the kernels compute), or the method's W with full
+    quotient and remainder products (clipped=False)."""
     from paper_2606_06386_amd import costmodel as cm
+    cost = cm.division_cost_clipped if clipped else cm.division_cost
     hs, nvs = prec_rows(u), prec_rows(v)
     total = 0
     cache = {}
     for h, nvv in zip(hs.tolist(), nvs.tolist()):
         key = (h, nvv - 1)
         if key not in cache:
-            cache[key] = cm.division_cost(h, nvv - 1) if nvv >= 2 and h >= nvv else 0
+            cache[key] = cost(h, nvv - 1) if nvv >= 2 and h >= nvv else 0
+        total += cache[key]
+    return total
+
+
+def ragged_limb_products(us, vs, clipped=True):
+    from paper_2606_06386_amd import costmodel as cm
+    cost = cm.division_cost_clipped if clipped else cm.division_cost
+    cache, total = {}, 0
+    for u, v in zip(us, vs):
+        key = (len(u), len(v) - 1)          # top limbs are nonzero in the mixed workload
+        if key not in cache:
+            cache[key] = cost(*key) if key[1] >= 1 and key[0] > key[1] else 0
         total += cache[key]
     return total
 
@@ -118,18 +142,178 @@ def probe_rates():
     print(json.dumps(out), flush=True)
 
 
+def _timed(fn, steps, stream):
+    import torch
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        fn()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = sorted(a.elapsed_time(b) for a, b in zip(starts, ends))
+    return elapsed, ms
+
+
+def run_mixed(args):
+    """The mixed-precision batch: one mp_divrem_ragged call per step."""
+    import torch
+    import oracle
+    from paper_2606_06386_amd import binding, inputs as I, ragged as R, tune
+    c = I.config_c4()
+    us, vs = c["u"], c["v"]
+    count = len(us)
+    tuned, fresh = tune.ensure(log=lambda m: print(m, file=sys.stderr, flush=True))
+    rb = binding.Ragged(R.pack(us, vs))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        rb.run(stream)
+    elapsed, ms = _timed(lambda: rb.run(stream), args.steps, stream)
+    kmean = sum(ms) / len(ms)
+
+    # the same divisions as four uniform launches (one per dividend width)
+    groups = []
+    for n in I.C4_WIDTHS:
+        js = [j for j in range(count) if len(us[j]) == n]
+        v = np.zeros((len(js), n), dtype=np.uint32)
+        for i, j in enumerate(js):
+            v[i, :len(vs[j])] = vs[j]
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+        ud, vd = t(np.stack([us[j] for j in js])), t(v)
+        out = (torch.empty((len(js), n), dtype=torch.int32, device="cuda"),
+               torch.empty((len(js), n), dtype=torch.int32, device="cuda"),
+               torch.empty(len(js), dtype=torch.int32, device="cuda"))
+        groups.append((ud, vd, out))
+
+    def plain():
+        for ud, vd, out in groups:
+            binding.divrem(ud, vd, out=out, stream=stream)
+    for _ in range(max(1, args.warmup // 4)):
+        plain()
+    _, pms = _timed(plain, max(3, args.steps // 4), stream)
+    pmean = sum(pms) / len(pms)
+
+    status = rb.status.cpu().numpy()
+    qp, rp = rb.q.cpu().numpy().view(np.uint32), rb.r.cpu().numpy().view(np.uint32)
+    packed_desc = np.frombuffer(rb.desc.cpu().numpy().tobytes(), dtype=R.DESC_DTYPE)
+    qs, rs = R.unpack(qp, packed_desc, "q"), R.unpack(rp, packed_desc, "r")
+    W = ragged_limb_products(us, vs)
+    achieved = W / (kmean * 1e-3)
+    algo_bytes = 4 * sum(2 * len(u) + 2 * len(v) for u, v in zip(us, vs)) + 4 * count + 48 * count
+    line = {
+        "metric": METRIC,
+        "value": count * args.steps / elapsed,
+        "unit": "div/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": c["name"], "bits": "2^15..2^18 mixed", "batch": count,
+                   "widths": list(I.C4_WIDTHS), "nv": "uniform in [ceil(n/4), n]"},
+        "kernel_ms": {"mean": kmean, "median": ms[len(ms) // 2], "min": ms[0]},
+        "uniform_launches_ms": {"mean": pmean, "min": pms[0]},
+        "tuned": {str(k): v for k, v in tuned.items()}, "tuned_now": fresh,
+        "limb_products_per_launch": W,
+        "limb_products_per_launch_full_products": ragged_limb_products(us, vs, clipped=False),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LIMB_PRODUCTS / 1e12,
+                     "unit": "T limb-products/s", "frac": achieved / PEAK_LIMB_PRODUCTS,
+                     "traffic": None, "traffic_unit": "bytes/launch",
+                     "algorithmic_bytes": algo_bytes, "kernel": "k_ragged (4 width classes)"},
+        "status_ok": int((status == 0).sum()),
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on the first instances (grouped by width), checked against the GPU
+        m, t_cpu, exact, used = 0, 0.0, 0, 0
+        while t_cpu < 10.0 and m < count:
+            js = list(range(m, min(count, m + 64)))
+            for n in I.C4_WIDTHS:
+                g = [j for j in js if len(us[j]) == n]
+                if not g:
+                    continue
+                v = np.zeros((len(g), n), dtype=np.uint32)
+                for i, j in enumerate(g):
+                    v[i, :len(vs[j])] = vs[j]
+                t0 = time.perf_counter()
+                qo, ro, so, used = oracle.divrem_threads(np.stack([us[j] for j in g]), v, n, n)
+                t_cpu += time.perf_counter() - t0
+                exact += sum(int((qo[i] == qs[j]).all() and (ro[i, :len(vs[j])] == rs[j]).all()
+                                 and not ro[i, len(vs[j]):].any()) for i, j in enumerate(g))
+            m = js[-1] + 1
+        line["cpu_baseline"] = {"value": m / t_cpu, "unit": "div/s", "cores": int(used), "kind": "oracle",
+                                "sample": f"first {m} of {count} instances of {c['name']} "
+                                          "(Knuth D, gcc -O2, OpenMP, per width)"}
+        line["parity_sample"] = f"{exact}/{m} bit-exact vs oracle"
+    print(json.dumps(line), flush=True)
+
+
+def serving_run(rate, count, ops=None, max_batch=2048, max_limbs=1 << 22):
+    """One serving run; returns its summary (latencies in ms)."""
+    from paper_2606_06386_amd import inputs as I, serve
+    c = ops if ops is not None else I.config_c5(rate, count=count)
+    arrival = I.c5_arrivals(rate, count)
+    res = serve.serve(c["u"], c["v"], arrival, max_batch=max_batch, max_limbs=max_limbs)
+    lat = res["latency"] * 1e3
+    st = res["backend"].status.cpu().numpy()
+    return {"rate_per_s": rate, "requests": count, "div_per_s": res["div_per_s"],
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_batch": float(np.mean(res["batches"])), "batches": len(res["batches"]),
+            "status_ok": int((st == 0).sum())}, res
+
+
+def run_serving(args):
+    from paper_2606_06386_amd import inputs as I, tune
+    import torch
+    count = 10000
+    tune.ensure(log=lambda m: print(m, file=sys.stderr, flush=True))
+    ops = I.config_c5(1e3, count=count)
+    rows = []
+    for rate in (1e3, 1e4, 1e5, 1e6):
+        row, res = serving_run(rate, count, ops)
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    # bit-exact sample of the last run against the oracle
+    import oracle
+    q, r, st = res["backend"].results()
+    js = list(range(0, count, max(1, count // 40)))
+    exact = 0
+    for j in js:
+        qo, ro, so = oracle.divrem(ops["u"][j][None, :], ops["v"][j][None, :], nq=len(ops["u"][j]),
+                                   nr=len(ops["v"][j]))
+        exact += int(so[0] == st[j] and (qo[0] == q[j]).all() and (ro[0] == r[j]).all())
+    top = rows[-1]
+    line = {
+        "metric": METRIC, "value": top["div_per_s"], "unit": "div/s", "n_gpus": 1, "steps": len(rows),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "serve_2p15_2p18_n%d" % count, "bits": "2^x, x ~ U[15, 18]",
+                   "nv": "uniform in [ceil(n/8), n]", "arrivals": "Poisson", "max_batch": 2048,
+                   "max_limbs": 1 << 22},
+        "serving": rows,
+        "parity_sample": f"{exact}/{len(js)} bit-exact vs oracle (rate 1e6 run)",
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", action="store_true", help="measure integer instruction issue rates instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: every division instance is independent and this "
-              "build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
+        print("bench.py measures one GPU: division instances are independent, so a multi-GPU "
+              "run would only split the batch; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -138,6 +322,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.probe:
         probe_rates()
+        return
+    if args.config == "c4":
+        run_mixed(args)
+        return
+    if args.config == "c5":
+        run_serving(args)
         return
     dev = torch.device("cuda:0")
     c = workload(args.config)
@@ -189,6 +379,7 @@ def main():
                    "nv": int(v_h.shape[1]), "nq": nq},
         "kernel_ms": {"mean": kmean, "median": kernel_ms[len(kernel_ms) // 2], "min": kernel_ms[0]},
         "limb_products_per_launch": W,
+        "limb_products_per_launch_full_products": limb_products(u_h, v_h, clipped=False),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LIMB_PRODUCTS / 1e12,
                      "unit": "T limb-products/s", "frac": achieved / PEAK_LIMB_PRODUCTS,
                      "traffic": measured_traffic(c["name"]), "traffic_unit": "bytes/launch",

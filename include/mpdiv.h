@@ -49,7 +49,7 @@ typedef enum {
     MP_ERR_DEVICE = 4   /* no usable gfx950 device */
 } mp_status_t;
 
-enum { MP_INST_OK = 0, MP_INST_DIVZERO = 1, MP_INST_QWIDTH = 2, MP_INST_INTERNAL = 3 };
+enum { MP_INST_OK = 0, MP_INST_DIVZERO = 1, MP_INST_QWIDTH = 2, MP_INST_INTERNAL = 3, MP_INST_BADDESC = 4 };
 
 /*
  * c = a * b for each instance: the classical (schoolbook) product, the
@@ -84,6 +84,50 @@ mp_status_t mp_shinv_batch(const uint32_t *v, int32_t nv, int32_t h, uint32_t *w
 mp_status_t mp_divrem_batch(const uint32_t *u, int32_t nu, const uint32_t *v, int32_t nv,
                             uint32_t *q, int32_t nq, uint32_t *r, int32_t *inst_status,
                             int32_t batch, void *stream);
+
+/*
+ * One division of a ragged (mixed-precision) batch: widths in limbs and limb
+ * offsets into packed pools.  u = u_pool[u_off .. u_off+nu), v = v_pool[v_off ..
+ * v_off+nv), q = q_pool[q_off .. q_off+nq), r = r_pool[r_off .. r_off+nv).
+ */
+typedef struct {
+    int64_t u_off, v_off, q_off, r_off;
+    int32_t nu, nv, nq, reserved;
+} mp_desc_t;
+
+/*
+ * Quotients and remainders of a batch of divisions of uneven precisions in one
+ * launch sequence (Alg. 3 per instance, as mp_divrem_batch).  On the device,
+ * instances are bucketed by dividend width into the classes <= 1024, <= 2048,
+ * <= 4096 and <= 8192 limbs; each class runs one persistent kernel whose
+ * workgroups take instances from a per-class work queue, the class kernels
+ * running concurrently.  Nothing is synchronised with the host, so the
+ * sequence can be captured into a hipGraph and replayed.
+ *   desc:      count descriptors (device memory);
+ *   *_limbs:   sizes of the four pools; a descriptor whose ranges leave its
+ *              pool or whose widths are outside [1, mp_max_limbs()] gets
+ *              MP_INST_BADDESC and its outputs are not written;
+ *   workspace: device memory of mp_ragged_workspace_bytes(count) bytes, owned
+ *              by the caller, not shared by concurrent calls;
+ *   inst_status: count int32 (required).
+ * Widths and offsets are checked on the device; null pointers and count < 0 on
+ * the host.
+ */
+mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint32_t *v_pool, int64_t v_limbs,
+                             const mp_desc_t *desc, uint32_t *q_pool, int64_t q_limbs, uint32_t *r_pool,
+                             int64_t r_limbs, int32_t *inst_status, int32_t count, void *workspace,
+                             void *stream);
+
+/* bytes of workspace mp_divrem_ragged needs for count instances */
+int64_t mp_ragged_workspace_bytes(int32_t count);
+
+/*
+ * Launch configuration of width class cls (0..3) for mp_divrem_ragged:
+ * threads per workgroup (256, 512 or 1024, at least width/8) and persistent
+ * workgroups per compute unit (1..8).  Returns MP_ERR_ARG for an invalid
+ * choice.  The defaults come from the library's tuned table.
+ */
+mp_status_t mp_ragged_config(int32_t cls, int32_t threads, int32_t wgs_per_cu);
 
 /* human-readable name of a status code (static storage) */
 const char *mp_status_str(mp_status_t s);

@@ -14,10 +14,11 @@ import torch
 from . import build as _build
 
 MP_OK, MP_ERR_ARG, MP_ERR_SIZE, MP_ERR_LAUNCH, MP_ERR_DEVICE = range(5)
-MP_INST_OK, MP_INST_DIVZERO, MP_INST_QWIDTH, MP_INST_INTERNAL = range(4)
+MP_INST_OK, MP_INST_DIVZERO, MP_INST_QWIDTH, MP_INST_INTERNAL, MP_INST_BADDESC = range(5)
 
 # every entry point declared in include/mpdiv.h
-EXPORTS = ("mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_status_str", "mp_max_limbs")
+EXPORTS = ("mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_divrem_ragged", "mp_ragged_workspace_bytes",
+           "mp_ragged_config", "mp_status_str", "mp_max_limbs")
 
 _lib = None
 _vp, _i32 = ctypes.c_void_p, ctypes.c_int32
@@ -40,6 +41,13 @@ def lib():
         L.mp_divrem_batch.argtypes = [_vp, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _i32, _vp]
         for f in (L.mp_mul_batch, L.mp_shinv_batch, L.mp_divrem_batch, L.mp_max_limbs):
             f.restype = _i32
+        _i64 = ctypes.c_int64
+        L.mp_divrem_ragged.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp]
+        L.mp_divrem_ragged.restype = _i32
+        L.mp_ragged_workspace_bytes.argtypes = [_i32]
+        L.mp_ragged_workspace_bytes.restype = _i64
+        L.mp_ragged_config.argtypes = [_i32, _i32, _i32]
+        L.mp_ragged_config.restype = _i32
         L.mp_max_limbs.argtypes = []
         L.mp_status_str.argtypes = [_i32]
         L.mp_status_str.restype = ctypes.c_char_p
@@ -113,3 +121,32 @@ def divrem(u, v, nq=None, out=None, stream=None):
     _raise(lib().mp_divrem_batch(u.data_ptr(), u.shape[1], v.data_ptr(), v.shape[1], q.data_ptr(), nq,
                                  r.data_ptr(), st.data_ptr(), batch, _stream(stream)), "mp_divrem_batch")
     return q, r, st
+
+
+class Ragged:
+    """Device-resident ragged batch (pools, descriptors, outputs, workspace)
+    built from ragged.pack(); run() launches mp_divrem_ragged."""
+
+    def __init__(self, packed, device="cuda"):
+        import numpy as np
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(device)
+        self.count = len(packed["desc"])
+        self.u = t(packed["u_pool"])
+        self.v = t(packed["v_pool"])
+        self.desc = torch.from_numpy(packed["desc"].view(np.uint8).copy()).to(device)
+        self.q = torch.zeros(packed["q_limbs"], dtype=torch.int32, device=device)
+        self.r = torch.zeros(packed["r_limbs"], dtype=torch.int32, device=device)
+        self.status = torch.zeros(self.count, dtype=torch.int32, device=device)
+        nb = int(lib().mp_ragged_workspace_bytes(self.count))
+        self.ws = torch.zeros((nb + 3) // 4, dtype=torch.int32, device=device)
+
+    def run(self, stream=None):
+        _raise(lib().mp_divrem_ragged(self.u.data_ptr(), self.u.numel(), self.v.data_ptr(), self.v.numel(),
+                                      self.desc.data_ptr(), self.q.data_ptr(), self.q.numel(), self.r.data_ptr(),
+                                      self.r.numel(), self.status.data_ptr(), self.count, self.ws.data_ptr(),
+                                      _stream(stream)), "mp_divrem_ragged")
+
+
+def ragged_config(cls, threads, wgs_per_cu):
+    """Launch configuration of width class cls (see mp_ragged_config)."""
+    _raise(lib().mp_ragged_config(cls, threads, wgs_per_cu), "mp_ragged_config")

@@ -11,6 +11,7 @@
 
 #include "../../include/mpdiv.h"
 
+#include <mutex>
 #include <string.h>
 
 namespace {
@@ -45,6 +46,76 @@ __global__ __launch_bounds__(T) void k_divrem(const uint32_t *u, int nu, const u
                            status ? status + j : nullptr);
 }
 
+// ------------------------------------------------------------ ragged batches
+//
+// Workspace (int32): [0, 4) instances per class, [4, 8) queue heads, then one
+// list of instance indices per class, each `count` long.
+constexpr int kClasses = 4;
+constexpr int kClassWidth[kClasses] = {1024, 2048, 4096, 8192};
+constexpr int kWsHeader = 16;
+
+__device__ __forceinline__ int width_class(int nu)
+{
+    return nu <= 1024 ? 0 : nu <= 2048 ? 1 : nu <= 4096 ? 2 : 3;
+}
+
+// one workgroup: validate descriptors and bucket instance indices by class
+__global__ __launch_bounds__(1024) void k_ragged_prep(const mp_desc_t *desc, int count, int64_t lu, int64_t lv,
+                                                      int64_t lq, int64_t lr, int32_t *status, int32_t *ws)
+{
+    __shared__ int cnt[kClasses];
+    if (threadIdx.x < kClasses) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < count; j += blockDim.x) {
+        const mp_desc_t d = desc[j];
+        const bool ok = d.nu >= 1 && d.nu <= kMaxLimbs && d.nv >= 1 && d.nv <= kMaxLimbs && d.nq >= 1 &&
+                        d.u_off >= 0 && d.v_off >= 0 && d.q_off >= 0 && d.r_off >= 0 &&
+                        d.u_off <= lu - d.nu && d.v_off <= lv - d.nv && d.q_off <= lq - d.nq &&
+                        d.r_off <= lr - d.nv;   // (no overflow: widths are small, offsets >= 0)
+        if (!ok) {
+            status[j] = MP_INST_BADDESC;
+            continue;
+        }
+        const int c = width_class(d.nu);
+        const int slot = atomicAdd(&cnt[c], 1);
+        ws[kWsHeader + (size_t)c * count + slot] = j;
+    }
+    __syncthreads();
+    if (threadIdx.x < kClasses) {
+        ws[threadIdx.x] = cnt[threadIdx.x];
+        ws[kClasses + threadIdx.x] = 0;
+    }
+}
+
+// persistent workgroups of one class: take the next instance of the class's
+// queue until it is empty
+template <int T>
+__global__ __launch_bounds__(T) void k_ragged(const uint32_t *up, const uint32_t *vp, const mp_desc_t *desc,
+                                              uint32_t *qp, uint32_t *rp, int32_t *status, int32_t *ws, int cls,
+                                              int count)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    const int n = ws[cls];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) lds[mp::kCtlBcast + 2] = (uint32_t)atomicAdd(&ws[kClasses + cls], 1);
+        __syncthreads();
+        const int idx = (int)lds[mp::kCtlBcast + 2];
+        if (idx >= n) break;
+        const int j = ws[kWsHeader + (size_t)cls * count + idx];
+        const mp_desc_t d = desc[j];
+        mp::divrem_instance<T>(lds, up + d.u_off, d.nu, vp + d.v_off, d.nv, qp + d.q_off, d.nq, rp + d.r_off,
+                               status + j);
+    }
+}
+
+struct RaggedConfig {
+    int threads[kClasses] = {256, 256, 512, 1024};
+    int wgs_per_cu[kClasses] = {6, 3, 2, 1};
+};
+RaggedConfig g_ragged;
+std::mutex g_ragged_mu;
+
 int threads_for(int width)
 {
     return width <= 2048 ? 256 : width <= 4096 ? 512 : 1024;
@@ -70,11 +141,32 @@ mp_status_t finish_launch()
     return hipGetLastError() == hipSuccess ? MP_OK : MP_ERR_LAUNCH;
 }
 
+// raise a kernel's dynamic LDS limit to at least `bytes` on the current
+// device; the attribute is set only when it grows, so repeated launches (and
+// launches under stream capture) make no further runtime call
 template <typename Kern>
 bool set_lds(Kern kernel, size_t bytes)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+    struct Entry {
+        const void *fn;
+        int dev;
+        size_t bytes;
+    };
+    static Entry seen[256];
+    static int nseen;
+    static std::mutex mu;
+    const void *fn = reinterpret_cast<const void *>(kernel);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lock(mu);
+    Entry *e = nullptr;
+    for (int i = 0; i < nseen; i++)
+        if (seen[i].fn == fn && seen[i].dev == dev) e = &seen[i];
+    if (e && e->bytes >= bytes) return true;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return false;
+    if (!e && nseen < 256) e = &seen[nseen++];
+    if (e) *e = Entry{fn, dev, bytes};
+    return true;
 }
 
 }  // namespace
@@ -182,6 +274,88 @@ mp_status_t mp_divrem_batch(const uint32_t *u, int32_t nu, const uint32_t *v, in
         break;
     }
     return finish_launch();
+}
+
+int64_t mp_ragged_workspace_bytes(int32_t count)
+{
+    return count < 0 ? 0 : (int64_t)4 * (kWsHeader + (int64_t)kClasses * count);
+}
+
+mp_status_t mp_ragged_config(int32_t cls, int32_t threads, int32_t wgs_per_cu)
+{
+    if (cls < 0 || cls >= kClasses || wgs_per_cu < 1 || wgs_per_cu > 8) return MP_ERR_ARG;
+    if (threads != 256 && threads != 512 && threads != 1024) return MP_ERR_ARG;
+    if (threads * 8 < kClassWidth[cls]) return MP_ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_ragged_mu);
+    g_ragged.threads[cls] = threads;
+    g_ragged.wgs_per_cu[cls] = wgs_per_cu;
+    return MP_OK;
+}
+
+mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint32_t *v_pool, int64_t v_limbs,
+                             const mp_desc_t *desc, uint32_t *q_pool, int64_t q_limbs, uint32_t *r_pool,
+                             int64_t r_limbs, int32_t *inst_status, int32_t count, void *workspace,
+                             void *stream)
+{
+    if (!u_pool || !v_pool || !desc || !q_pool || !r_pool || !inst_status || !workspace || count < 0)
+        return MP_ERR_ARG;
+    if (u_limbs < 0 || v_limbs < 0 || q_limbs < 0 || r_limbs < 0) return MP_ERR_ARG;
+    if (count == 0) return MP_OK;
+    if (!device_ok()) return MP_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_ragged_mu);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MP_ERR_DEVICE;
+    // per-device fork streams and events (default priority), made once
+    static hipStream_t fork[64][kClasses];
+    static hipEvent_t ev_fork[64], ev_join[64][kClasses];
+    static int cus[64];
+    if (cus[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MP_ERR_DEVICE;
+        for (int c = 0; c < kClasses; c++) {
+            if (hipStreamCreateWithFlags(&fork[dev][c], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ev_join[dev][c], hipEventDisableTiming) != hipSuccess)
+                return MP_ERR_LAUNCH;
+        }
+        if (hipEventCreateWithFlags(&ev_fork[dev], hipEventDisableTiming) != hipSuccess) return MP_ERR_LAUNCH;
+        cus[dev] = prop.multiProcessorCount;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *ws = (int32_t *)workspace;
+    hipLaunchKernelGGL(k_ragged_prep, dim3(1), dim3(1024), 0, st, desc, count, u_limbs, v_limbs, q_limbs,
+                       r_limbs, inst_status, ws);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(ev_fork[dev], st) != hipSuccess) return MP_ERR_LAUNCH;
+    for (int c = 0; c < kClasses; c++) {
+        hipStream_t fs = fork[dev][c];
+        if (hipStreamWaitEvent(fs, ev_fork[dev], 0) != hipSuccess) return MP_ERR_LAUNCH;
+        const int T = g_ragged.threads[c];
+        const size_t bytes = (size_t)mp::div_lds_words(kClassWidth[c], kClassWidth[c], T) * 4;
+        if (bytes > (size_t)kLdsWords * 4) return MP_ERR_SIZE;
+        const int fit = (int)(((size_t)kLdsWords * 4) / bytes);
+        const int wpc = g_ragged.wgs_per_cu[c] < fit ? g_ragged.wgs_per_cu[c] : fit;
+        const dim3 grid(cus[dev] * wpc);
+        switch (T) {
+        case 256:
+            if (!set_lds(k_ragged<256>, bytes)) return MP_ERR_LAUNCH;
+            hipLaunchKernelGGL(k_ragged<256>, grid, dim3(256), bytes, fs, u_pool, v_pool, desc, q_pool, r_pool,
+                               inst_status, ws, c, count);
+            break;
+        case 512:
+            if (!set_lds(k_ragged<512>, bytes)) return MP_ERR_LAUNCH;
+            hipLaunchKernelGGL(k_ragged<512>, grid, dim3(512), bytes, fs, u_pool, v_pool, desc, q_pool, r_pool,
+                               inst_status, ws, c, count);
+            break;
+        default:
+            if (!set_lds(k_ragged<1024>, bytes)) return MP_ERR_LAUNCH;
+            hipLaunchKernelGGL(k_ragged<1024>, grid, dim3(1024), bytes, fs, u_pool, v_pool, desc, q_pool, r_pool,
+                               inst_status, ws, c, count);
+            break;
+        }
+        if (hipGetLastError() != hipSuccess || hipEventRecord(ev_join[dev][c], fs) != hipSuccess ||
+            hipStreamWaitEvent(st, ev_join[dev][c], 0) != hipSuccess)
+            return MP_ERR_LAUNCH;
+    }
+    return MP_OK;
 }
 
 }  // extern "C"

@@ -189,3 +189,51 @@ def config_c3(batch=256, index=None):
     v = limbs_top_nonzero(substream(st, 1), n, nv_eff - 1)
     return {"name": "divrem_2p18_b256", "u": u, "v": v, "nq": 6145, "bits": 1 << 18,
             "nv_eff": nv_eff, "index": idx}
+
+
+C4_WIDTHS = (1024, 2048, 4096, 8192)   # 2^15 .. 2^18 bits
+
+
+def config_c4(count=8192, index=None):
+    """Mixed precisions: dividend width uniform over {1024, 2048, 4096, 8192}
+    limbs (top limb nonzero), divisor length uniform in [ceil(n/4), n] limbs
+    (top limb nonzero).  Returns per-instance lists of u and v rows."""
+    idx = np.arange(count) if index is None else np.asarray(index, dtype=np.int64)
+    st = instance_states(SEED_C4, idx)
+    s2 = substream(st, 2)
+    ns = np.asarray(C4_WIDTHS)[uniform_int(s2, 0, 3, draw_index=0)]
+    nvs = np.array([int(uniform_int(s2[r:r + 1], (n + 3) // 4, n, draw_index=1)[0]) for r, n in enumerate(ns)])
+    s0, s1 = substream(st, 0), substream(st, 1)
+    us = [limbs_top_nonzero(s0[r:r + 1], int(n))[0] for r, n in enumerate(ns)]
+    vs = [limbs_top_nonzero(s1[r:r + 1], int(nv))[0] for r, nv in enumerate(nvs)]
+    return {"name": "divrem_mixed_2p15_2p18_b%d" % len(idx), "u": us, "v": vs, "n": ns, "nv": nvs,
+            "index": idx}
+
+
+def config_c5(rate, count=10000, index=None):
+    """Serving workload: request j arrives after exponential gaps of mean
+    1/rate seconds (Poisson arrivals); its dividend has n = round(2^x / 32)
+    limbs with x uniform in [15, 18] (top limb nonzero) and its divisor a
+    length uniform in [ceil(n/8), n] (top limb nonzero).  The operands do not
+    depend on the rate; the arrival times do."""
+    idx = np.arange(count) if index is None else np.asarray(index, dtype=np.int64)
+    st = instance_states(SEED_C5, idx)
+    s2 = substream(st, 2)
+    x = 15.0 + 3.0 * (draws(s2, 0, 1)[:, 0] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    ns = np.rint(2.0 ** x / 32.0).astype(np.int64)
+    nvs = np.array([int(uniform_int(s2[r:r + 1], (n + 7) // 8, n, draw_index=1)[0]) for r, n in enumerate(ns)])
+    s0, s1 = substream(st, 0), substream(st, 1)
+    us = [limbs_top_nonzero(s0[r:r + 1], int(n))[0] for r, n in enumerate(ns)]
+    vs = [limbs_top_nonzero(s1[r:r + 1], int(nv))[0] for r, nv in enumerate(nvs)]
+    arrival = c5_arrivals(rate, int(idx.max()) + 1)[idx] if len(idx) else np.zeros(0)
+    return {"name": "serve_2p15_2p18_rate%g_n%d" % (rate, len(idx)), "u": us, "v": vs, "n": ns, "nv": nvs,
+            "arrival": arrival, "rate": rate, "index": idx}
+
+
+def c5_arrivals(rate, count):
+    """Arrival times (s) of the first `count` serving requests at `rate` per
+    second: cumulative exponential gaps drawn from a generator of their own
+    (seeded by the rate), gap = -ln(U) / rate with U uniform in (0, 1)."""
+    ga = draws(np.array([np.uint64(SEED_C5 ^ int(rate * 1000))], dtype=np.uint64), 0, count)[0]
+    uni = ((ga >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+    return np.cumsum(-np.log(uni) / rate)

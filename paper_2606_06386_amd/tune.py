@@ -1,0 +1,115 @@
+"""Autotuner for the launch configuration of mixed-precision batches.
+
+For each dividend width class of mp_divrem_ragged (<= 1024, 2048, 4096, 8192
+limbs) it times a one-class batch of seeded random divisions under every
+valid (threads per workgroup, persistent workgroups per compute unit) and
+installs the fastest with mp_ragged_config.  Results are cached in a JSON
+file keyed by the device (architecture name and compute-unit count) and by a
+hash of the kernel sources, so a cache entry is never applied to a different
+chip or to changed kernels.  Timing runs on the GPU; nothing here computes
+any part of a division.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+
+from . import inputs as I
+
+CLASS_WIDTHS = (1024, 2048, 4096, 8192)
+THREADS = (256, 512, 1024)
+WGS_PER_CU = (1, 2, 3, 4, 6, 8)
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_ragged.json")
+_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(_CSRC)):
+        with open(os.path.join(_CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def device_key():
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return "%s/%dcu/%s" % (p.gcnArchName.split(":")[0], p.multi_processor_count, source_hash())
+
+
+def candidates(cls):
+    w = CLASS_WIDTHS[cls]
+    return [(t, g) for t in THREADS if 8 * t >= w for g in WGS_PER_CU]
+
+
+def class_batch(cls, count):
+    """Seeded one-class divisions: width n of the class, divisor length
+    uniform in [ceil(n/4), n] (the mixed workload's distribution)."""
+    n = CLASS_WIDTHS[cls]
+    st = I.instance_states(I.SEED_C4 ^ (0x7E0000 + cls), np.arange(count))
+    nvs = I.uniform_int(I.substream(st, 2), (n + 3) // 4, n)
+    s0, s1 = I.substream(st, 0), I.substream(st, 1)
+    us = list(I.limbs_top_nonzero(s0, n))
+    vs = [I.limbs_top_nonzero(s1[r:r + 1], int(nv))[0] for r, nv in enumerate(nvs)]
+    return us, vs
+
+
+def _time(rb, reps):
+    import torch
+    rb.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rb.run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(counts=(2048, 1024, 512, 256), reps=3, log=None):
+    """Time every candidate per class; returns {cls: (threads, wgs_per_cu, ms)}."""
+    from . import binding, ragged
+    best = {}
+    for cls in range(len(CLASS_WIDTHS)):
+        us, vs = class_batch(cls, counts[cls])
+        rb = binding.Ragged(ragged.pack(us, vs))
+        times = []
+        for t, g in candidates(cls):
+            binding.ragged_config(cls, t, g)
+            ms = _time(rb, reps)
+            times.append((ms, t, g))
+            if log:
+                log("class %d (<= %d limbs): threads %d, %d WG/CU: %.3f ms" % (cls, CLASS_WIDTHS[cls], t, g, ms))
+        ms, t, g = min(times)
+        binding.ragged_config(cls, t, g)
+        best[cls] = (t, g, ms)
+    return best
+
+
+def apply(entry):
+    from . import binding
+    for cls, (t, g, _) in entry.items():
+        binding.ragged_config(int(cls), int(t), int(g))
+
+
+def ensure(cache=DEFAULT_CACHE, log=None):
+    """Install the cached configuration for this device, tuning (and writing
+    the cache, where writable) when there is none."""
+    key = device_key()
+    data = {}
+    if os.path.exists(cache):
+        with open(cache) as fh:
+            data = json.load(fh)
+    if key in data:
+        apply({int(k): v for k, v in data[key].items()})
+        return data[key], False
+    best = tune(log=log)
+    data[key] = {str(k): list(v) for k, v in best.items()}
+    try:
+        with open(cache, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+    except OSError:
+        pass
+    return data[key], True

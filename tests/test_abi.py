@@ -25,7 +25,8 @@ def L():
 
 def test_exports_every_declared_symbol(L):
     names = _declared()
-    assert set(names) == {"mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_status_str", "mp_max_limbs"}
+    assert set(names) == {"mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_divrem_ragged",
+                          "mp_ragged_workspace_bytes", "mp_ragged_config", "mp_status_str", "mp_max_limbs"}
     for n in names:
         assert hasattr(L, n), n
     from paper_2606_06386_amd import binding
@@ -53,20 +54,33 @@ def test_host_argument_errors(L):
     assert L.mp_shinv_batch(p, 4, -1, p, 4, None, 1, None) == MP_ERR_ARG
     assert L.mp_shinv_batch(p, 4, 8193, p, 4, None, 1, None) == MP_ERR_SIZE
     assert L.mp_shinv_batch(p, 4, 10, p, 11, None, 0, None) == MP_OK
+    # ragged batch: pointers and count are checked on the host
+    assert L.mp_divrem_ragged(None, 4, p, 4, p, p, 4, p, 4, p, 1, p, None) == MP_ERR_ARG
+    assert L.mp_divrem_ragged(p, 4, p, 4, p, p, 4, p, 4, None, 1, p, None) == MP_ERR_ARG
+    assert L.mp_divrem_ragged(p, 4, p, 4, p, p, 4, p, 4, p, 1, None, None) == MP_ERR_ARG
+    assert L.mp_divrem_ragged(p, 4, p, 4, p, p, 4, p, 4, p, -1, p, None) == MP_ERR_ARG
+    assert L.mp_divrem_ragged(p, 4, p, 4, p, p, 4, p, 4, p, 0, p, None) == MP_OK
+    assert L.mp_ragged_workspace_bytes(0) > 0
+    assert L.mp_ragged_workspace_bytes(1000) >= 4 * 1000 * 4
+    assert L.mp_ragged_config(4, 256, 1) == MP_ERR_ARG
+    assert L.mp_ragged_config(0, 384, 1) == MP_ERR_ARG
+    assert L.mp_ragged_config(3, 512, 1) == MP_ERR_ARG      # 8192 limbs need at least 1024 threads
+    assert L.mp_ragged_config(0, 256, 0) == MP_ERR_ARG
+    assert L.mp_ragged_config(0, 256, 9) == MP_ERR_ARG
 
 
 def test_lds_plan_bounds():
     """The per-instance LDS plan (mirrored here from mp_div.hpp's plan_div for
     the host-side size check) stays within gfx950's 160 KB at 2^18 bits."""
     from paper_2606_06386_amd import costmodel  # noqa: F401  (importable without a GPU)
-    pad, ctl = 264, 256
+    pad, ctl, xpad = 264, 256, 16
     r4 = lambda x: (x + 3) & ~3
     worst = 0
     h = 8192
     for k in range(1, h):
         d = h - k
-        tot = (ctl + r4(k + 1) + r4(d + 8) + r4(k + 12) + pad + r4(max(h, k + 12, d + 8) + 4) + pad
-               + r4(max(2 * h - k + 1, h + 8) + 4) + 4)
+        tot = (ctl + r4(k + 1) + r4(d + 8) + r4(k + 12) + xpad + r4(h // 2 + 16) + xpad + pad
+               + r4(max(h, k + 12, d + 8) + 4) + pad + r4(max(2 * h - k + 1, h + 8) + 4) + 4)
         worst = max(worst, tot)
     assert worst * 4 <= 160 * 1024
 
@@ -82,3 +96,20 @@ def test_cost_model_values():
     assert cm.division_cost(2048, 1023) == 4391342
     assert cm.low_product_cost(3, 5, 7) == 15 and cm.low_product_cost(3, 5, 2) == 3
     assert cm.division_cost(10, 10) == 0 and cm.division_cost(10, 0) == 0
+
+
+def test_cost_model_clipped():
+    """Clipped products: column counts by enumeration on small shapes, and the
+    quotient/remainder products roughly halved at 2^16 bits."""
+    from paper_2606_06386_amd import costmodel as cm
+    for a, b in [(3, 5), (7, 7), (9, 4), (1, 6)]:
+        for c in range(a + b + 1):
+            pairs = [(i, j) for i in range(a) for j in range(b)]
+            assert cm.low_product_cost(a, b, c) == sum(1 for i, j in pairs if i + j < c)
+            assert cm.high_product_cost(a, b, c) == sum(1 for i, j in pairs if i + j >= c)
+    h, k = 2048, 1023
+    d = h - k
+    assert cm.division_cost_clipped(h, k) == 1777660
+    assert cm.division_cost_clipped(h, k) - cm.refine_cost(h, k, True) < 0.6 * (h * d + (k + 1) * d)
+    assert cm.refine_cost(h, k, True) < 0.6 * cm.refine_cost(h, k)
+    assert cm.division_cost_clipped(10, 10) == 0

@@ -61,3 +61,32 @@ def test_c2_adversarial_families():
 def test_limb_conversions_roundtrip():
     x = (1 << 200) + 12345678901234567890
     assert I.to_int(I.from_int(x, 8)) == x
+
+
+def test_config_c4_mixed_widths():
+    """Mixed-precision workload: widths from the four classes, divisor lengths
+    in [ceil(n/4), n], top limbs nonzero, any instance regenerable alone."""
+    c = I.config_c4(count=256)
+    assert set(int(n) for n in c["n"]) == set(I.C4_WIDTHS)
+    for u, v, n, nv in zip(c["u"], c["v"], c["n"], c["nv"]):
+        assert len(u) == n and len(v) == nv and (n + 3) // 4 <= nv <= n
+        assert u[-1] != 0 and v[-1] != 0
+    one = I.config_c4(index=[77])
+    assert (one["u"][0] == c["u"][77]).all() and (one["v"][0] == c["v"][77]).all()
+
+
+def test_ragged_pack_roundtrip():
+    from paper_2606_06386_amd import ragged as R
+    c = I.config_c4(count=40)
+    p = R.pack(c["u"], c["v"])
+    d = p["desc"]
+    for f in ("u_off", "v_off", "q_off", "r_off"):
+        assert (d[f] % 4 == 0).all()
+    # ranges are disjoint and inside their pools
+    for off, n, size in ((d["u_off"], d["nu"], len(p["u_pool"])), (d["q_off"], d["nq"], p["q_limbs"]),
+                         (d["r_off"], d["nv"], p["r_limbs"])):
+        order = np.argsort(off)
+        ends = off[order] + n[order]
+        assert (ends[:-1] <= off[order][1:]).all() and ends[-1] <= size
+    us = R.unpack(p["u_pool"], np.rec.fromarrays([d["u_off"], d["nu"]], names="q_off,nq"), "q")
+    assert all((a == b).all() for a, b in zip(us, c["u"]))
