@@ -30,11 +30,19 @@ if ROOT not in sys.path:
 
 METRIC = "divisions/sec at 2^16-bit u (bit-exact) + % int-mul roofline; serving p99 latency"
 
-# Integer-multiply roofline of MI355X: 256 CUs x 4 SIMDs at 2.4 GHz, each SIMD
-# issuing one wave64 v_mad_u64_u32 (64 limb products of 32x32->64 bits) every
-# 4 cycles, i.e. 64 limb products per clock per CU.  (Simple 32-bit ALU ops
-# such as v_add_u32 issue twice as fast on gfx950; the probe mode measures both.)
+# The products run on the int8 matrix cores: one 32x32-bit limb product is 16
+# digit products (4 x 4 bytes), i.e. 32 int8 operations.  MI355X's published
+# dense int8 matrix peak is 5.0e15 operations/s.
+OPS_PER_LIMB_PRODUCT = 32
+PEAK_INT8_OPS = 5.0e15
+# For comparison, the vector-ALU multiply rate: 256 CUs x 4 SIMDs at 2.4 GHz,
+# each SIMD issuing one wave64 v_mad_u64_u32 (64 limb products) every 4 cycles.
 PEAK_LIMB_PRODUCTS = 256 * 4 * 16 * 2.4e9
+
+
+def threads_for(width):
+    """Workgroup size the library launches for dividends of `width` limbs."""
+    return 256 if width <= 2048 else 512 if width <= 4096 else 1024
 
 
 def prec_rows(x):
@@ -86,9 +94,53 @@ def measured_traffic(workload_name):
     path = os.path.join(ROOT, "profiles", f"k_divrem_{workload_name.split('_', 1)[1]}_traffic.json")
     if not os.path.exists(path):
         return None
+    if not os.path.exists(path):
+        return None
     rec = json.load(open(path))
-    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in rec["sources"])).hexdigest()
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s_), "rb").read() for s_ in rec["sources"])).hexdigest()
     return rec["traffic_bytes_per_dispatch"] if h == rec["source_sha256"] else None
+
+
+TRAFFIC_SOURCES = ["paper_2606_06386_amd/csrc/mp_prims_hip.hpp", "paper_2606_06386_amd/csrc/mp_core.hpp",
+                   "paper_2606_06386_amd/csrc/mp_div.hpp", "paper_2606_06386_amd/csrc/mpdiv.hip"]
+
+
+def write_traffic(fetch_csv, write_csv, workload_name, kernel="k_divrem<"):
+    """profiles/k_divrem_<workload>_traffic.json from two rocprofv3 --pmc
+    counter files (FETCH_SIZE, WRITE_SIZE) of `bench.py --copy-calibration`:
+    the kernel's mean KiB per dispatch, each scaled by what the same counter
+    reads for the 256 MiB device copy."""
+    import csv
+    import hashlib
+
+    def read(path, counter):
+        kern, copy = [], []
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                v = float(row["Counter_Value"])
+                if kernel in row["Kernel_Name"]:
+                    kern.append(v)
+                elif "copyBuffer" in row["Kernel_Name"]:
+                    copy.append(v)
+        assert kern and copy, (path, counter, len(kern), len(copy))
+        return sum(kern) / len(kern), max(copy)    # the 256 MiB copy is the largest
+
+    f_k, f_c = read(fetch_csv, "FETCH_SIZE")
+    w_k, w_c = read(write_csv, "WRITE_SIZE")
+    nbytes = 256 << 20
+    ff, wf = nbytes / 1024 / f_c, nbytes / 1024 / w_c
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s_), "rb").read() for s_ in TRAFFIC_SOURCES)).hexdigest()
+    rec = {"kernel": kernel, "workload": workload_name, "fetch_size_kib_per_dispatch": f_k,
+           "write_size_kib_per_dispatch": w_k,
+           "copy_calibration": {"bytes": nbytes, "fetch_size_kib": f_c, "write_size_kib": w_c},
+           "fetch_factor": ff, "write_factor": wf, "traffic_bytes_per_dispatch": 1024 * (f_k * ff + w_k * wf),
+           "source_sha256": h, "sources": TRAFFIC_SOURCES}
+    path = os.path.join(ROOT, "profiles", f"k_divrem_{workload_name.split('_', 1)[1]}_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
 
 
 def cpu_baseline(c, q_gpu, r_gpu, budget_s=10.0):
@@ -158,6 +210,16 @@ def _timed(fn, steps, stream):
     return elapsed, ms
 
 
+def roofline(W, ms, kernel, traffic, algo_bytes):
+    """Roofline object of a launch doing W limb products in ms milliseconds."""
+    ops = OPS_PER_LIMB_PRODUCT * W / (ms * 1e-3)
+    return {"bound": "mfma", "achieved": ops / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TFLOP/s",
+            "op": "int8 matrix operations (32 per 32x32-bit limb product)", "frac": ops / PEAK_INT8_OPS,
+            "traffic": traffic, "traffic_unit": "bytes/launch", "algorithmic_bytes": algo_bytes,
+            "kernel": kernel, "limb_products_per_s": W / (ms * 1e-3),
+            "valu_mad_peak_limb_products_per_s": PEAK_LIMB_PRODUCTS}
+
+
 def run_mixed(args):
     """The mixed-precision batch: one mp_divrem_ragged call per step."""
     import torch
@@ -201,7 +263,6 @@ def run_mixed(args):
     packed_desc = np.frombuffer(rb.desc.cpu().numpy().tobytes(), dtype=R.DESC_DTYPE)
     qs, rs = R.unpack(qp, packed_desc, "q"), R.unpack(rp, packed_desc, "r")
     W = ragged_limb_products(us, vs)
-    achieved = W / (kmean * 1e-3)
     algo_bytes = 4 * sum(2 * len(u) + 2 * len(v) for u, v in zip(us, vs)) + 4 * count + 48 * count
     line = {
         "metric": METRIC,
@@ -223,10 +284,7 @@ def run_mixed(args):
         "tuned": {str(k): v for k, v in tuned.items()}, "tuned_now": fresh,
         "limb_products_per_launch": W,
         "limb_products_per_launch_full_products": ragged_limb_products(us, vs, clipped=False),
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LIMB_PRODUCTS / 1e12,
-                     "unit": "T limb-products/s", "frac": achieved / PEAK_LIMB_PRODUCTS,
-                     "traffic": None, "traffic_unit": "bytes/launch",
-                     "algorithmic_bytes": algo_bytes, "kernel": "k_ragged (4 width classes)"},
+        "roofline": roofline(W, kmean, "k_ragged (4 width classes)", None, algo_bytes),
         "status_ok": int((status == 0).sum()),
     }
     if not args.no_cpu_baseline:
@@ -310,7 +368,16 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", action="store_true", help="measure integer instruction issue rates instead")
+    ap.add_argument("--no-serving", action="store_true", help="skip the short serving run")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic record of --config's workload from two counter files and exit")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic, workload_name={"c1": "divrem_2p15_b1024", "c2": "divrem_2p16_b4096",
+                                                          "c3": "divrem_2p18_b256"}[args.config])
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: division instances are independent, so a multi-GPU "
               "run would only split the batch; --gpus must be 1", file=sys.stderr)
@@ -360,7 +427,6 @@ def main():
     status = st.cpu().numpy()
     q_h, r_h = q.cpu().numpy().view(np.uint32), r.cpu().numpy().view(np.uint32)
     W = limb_products(u_h, v_h)
-    achieved = W / (kmean * 1e-3)
     algo_bytes = 4 * (u_h.size + v_h.size + q_h.size + r_h.size) + 4 * batch   # u, v in; q, r, status out
     line = {
         "metric": METRIC,
@@ -380,12 +446,22 @@ def main():
         "kernel_ms": {"mean": kmean, "median": kernel_ms[len(kernel_ms) // 2], "min": kernel_ms[0]},
         "limb_products_per_launch": W,
         "limb_products_per_launch_full_products": limb_products(u_h, v_h, clipped=False),
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LIMB_PRODUCTS / 1e12,
-                     "unit": "T limb-products/s", "frac": achieved / PEAK_LIMB_PRODUCTS,
-                     "traffic": measured_traffic(c["name"]), "traffic_unit": "bytes/launch",
-                     "algorithmic_bytes": algo_bytes, "kernel": "k_divrem"},
+        "roofline": roofline(W, kmean, "k_divrem<%d>" % threads_for(u_h.shape[1]), measured_traffic(c["name"]),
+                             algo_bytes),
         "status_ok": int((status == 0).sum()),
     }
+    if args.copy_calibration:
+        x = torch.empty(64 << 20, dtype=torch.int32, device=dev)
+        y = torch.ones_like(x)
+        x.copy_(y)
+        torch.cuda.synchronize()
+    if not args.no_serving:
+        # serving latency beside the throughput: 10^4 requests of 2^15..2^18
+        # bits arriving at 10^5 per second (outside the timed region)
+        from paper_2606_06386_amd import tune
+        tune.ensure()
+        row, _ = serving_run(1e5, 10000)
+        line["serving"] = row
     if not args.no_cpu_baseline:
         cb, exact, n = cpu_baseline(c, q_h, r_h)
         line["cpu_baseline"] = cb
