@@ -155,16 +155,21 @@ MP_DEV void wg_max_n(uint32_t *ctl, uint32_t (&x)[N])
     }
 }
 
-// max over k in [0, n) of f(k)  (f(k) >= 0)
+MP_DEV uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+
+// max over k in [0, n) of f(k)  (f(k) >= 0).  Four independent reads per
+// step, so their latencies overlap.
 template <int T, class F>
 MP_DEV int reduce_max(uint32_t *ctl, int n, const F &f)
 {
     sync();
     uint32_t m = 0;
-    for (int k = tid(); k < n; k += T) {
-        uint32_t y = f(k);
-        m = m > y ? m : y;
+    int k = tid();
+    for (; k + 3 * T < n; k += 4 * T) {
+        const uint32_t y0 = f(k), y1 = f(k + T), y2 = f(k + 2 * T), y3 = f(k + 3 * T);
+        m = umax(m, umax(umax(y0, y1), umax(y2, y3)));
     }
+    for (; k < n; k += T) m = umax(m, f(k));
     return (int)wg_max<T>(ctl, m);
 }
 
@@ -206,15 +211,26 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
                              const FX &x, const FY &y, const FO &out)
 {
     constexpr int W = T / kLanes;
+    constexpr bool kPre = CM <= 9;   // short chunks: all reads first, so their latencies overlap
+    constexpr int CP = kPre ? CM : 1;
     const int k0 = tid() * C;
-    uint32_t z[CM];
+    uint32_t z[CM], av[CP], bv[CP];
     uint32_t c = 0;
     bool prop = true;
+    if (kPre) {
+#pragma unroll
+        for (int j = 0; j < CP; j++) {
+            const int k = k0 + j;
+            const bool in = j < C && k < n;
+            av[j] = in ? x(k) : 0u;
+            bv[j] = in ? y(k) : 0u;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < CM; j++) {
         const int k = k0 + j;
         if (j < C && k < n) {
-            const uint32_t a = x(k), b = y(k);
+            const uint32_t a = kPre ? av[j < CP ? j : 0] : x(k), b = kPre ? bv[j < CP ? j : 0] : y(k);
             if (!sub) {
                 uint64_t s = (uint64_t)a + b + c;
                 z[j] = (uint32_t)s;
@@ -295,7 +311,8 @@ MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
     const int C = ((n + T - 1) / T) | 1;
     if (C == 1) return addsub_chunk<T, 1>(ctl, n, C, sub, cin, x, y, out);
     if (C == 3) return addsub_chunk<T, 3>(ctl, n, C, sub, cin, x, y, out);
-    if (C <= 7) return addsub_chunk<T, 7>(ctl, n, C, sub, cin, x, y, out);
+    if (C <= 5) return addsub_chunk<T, 5>(ctl, n, C, sub, cin, x, y, out);
+    if (C <= 9) return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out);
     return addsub_chunk<T, kCMax>(ctl, n, C, sub, cin, x, y, out);
 }
 
@@ -305,7 +322,16 @@ MP_DEV void copy(uint32_t *dst, int n, int clear, const FS &src)
 {
     sync();
     const int e = imax(n, clear);
-    for (int k = tid(); k < e; k += T) dst[k] = k < n ? src(k) : 0u;
+    int k = tid();
+    for (; k + 3 * T < e; k += 4 * T) {
+        const uint32_t y0 = k < n ? src(k) : 0u, y1 = k + T < n ? src(k + T) : 0u;
+        const uint32_t y2 = k + 2 * T < n ? src(k + 2 * T) : 0u, y3 = k + 3 * T < n ? src(k + 3 * T) : 0u;
+        dst[k] = y0;
+        dst[k + T] = y1;
+        dst[k + 2 * T] = y2;
+        dst[k + 3 * T] = y3;
+    }
+    for (; k < e; k += T) dst[k] = k < n ? src(k) : 0u;
 }
 
 // ------------------------------------------------------------- multiply

@@ -124,7 +124,16 @@ MP_DEV bool store_fit(uint32_t *ctl, uint32_t *dst, int n, int ext, const FS &sr
 {
     const int e = prec<T>(ctl, ext, src);
     if (e > n) return false;
-    for (int i = tid(); i < n; i += T) dst[i] = i < e ? src(i) : 0u;
+    int i = tid();
+    for (; i + 3 * T < n; i += 4 * T) {
+        const uint32_t y0 = i < e ? src(i) : 0u, y1 = i + T < e ? src(i + T) : 0u;
+        const uint32_t y2 = i + 2 * T < e ? src(i + 2 * T) : 0u, y3 = i + 3 * T < e ? src(i + 3 * T) : 0u;
+        dst[i] = y0;
+        dst[i + T] = y1;
+        dst[i + 2 * T] = y2;
+        dst[i + 3 * T] = y3;
+    }
+    for (; i < n; i += T) dst[i] = i < e ? src(i) : 0u;
     return true;
 }
 
@@ -383,11 +392,26 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     // one pass over u and v: prec(u), prec(v), and the lowest nonzero limb of v
     uint32_t red[3] = {0u, 0u, 0u};
     sync();
-    for (int i = tid(); i < (nu > nv ? nu : nv); i += T) {
-        if (i < nu && u[i]) red[0] = (uint32_t)(i + 1);
-        if (i < nv && v[i]) {
-            red[1] = (uint32_t)(i + 1);
-            red[2] = red[2] ? red[2] : (uint32_t)(nv - i);
+    {
+        // four limbs of u and of v per thread and step, all read before use
+        const int nm = nu > nv ? nu : nv;
+        for (int i0 = tid(); i0 < nm; i0 += 4 * T) {
+            uint32_t ua[4], va[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int i = i0 + j * T;
+                ua[j] = i < nu ? u[i] : 0u;
+                va[j] = i < nv ? v[i] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int i = i0 + j * T;
+                if (ua[j]) red[0] = (uint32_t)(i + 1);
+                if (va[j]) {
+                    red[1] = (uint32_t)(i + 1);
+                    red[2] = red[2] ? red[2] : (uint32_t)(nv - i);
+                }
+            }
         }
     }
     wg_max_n<T, 3>(ctl, red);
@@ -423,10 +447,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
         uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP, *XR = lds + pl.offR;
         // V = v; W, X, R and the window staging area (with its guards) = 0
-        for (int i = tid(); i < pl.offP - pl.offV; i += T) {
-            const int o = pl.offV + i;
-            V[i] = o < pl.offW ? (i <= k ? v[i] : 0u) : 0u;
-        }
+        copy<T>(V, k + 1, pl.offP - pl.offV, Vg);
         int we = 0, nw = 0, shf = 0, sbext = 0;
         bool good = true;
         if (k == h - 1 && (vk > 0x80000000u || (vk == 0x80000000u && !lowz))) {

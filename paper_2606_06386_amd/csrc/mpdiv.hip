@@ -17,6 +17,11 @@
 namespace {
 
 constexpr int kMaxLimbs = 8192;
+
+// Division kernels ask the compiler for at most 128 registers per lane, so
+// that four waves share each SIMD: four 256-thread workgroups per compute
+// unit at 2^16 bits, where the LDS plan also allows four.
+#define MP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4, 8)))
 constexpr int kLdsWords = 160 * 1024 / 4;   // gfx950: 160 KB of LDS per workgroup
 
 template <int T>
@@ -28,7 +33,7 @@ __global__ __launch_bounds__(T) void k_mul(const uint32_t *a, int na, const uint
 }
 
 template <int T>
-__global__ __launch_bounds__(T) void k_shinv(const uint32_t *v, int nv, int h, uint32_t *w, int nw,
+__global__ __launch_bounds__(T) MP_OCCUPANCY void k_shinv(const uint32_t *v, int nv, int h, uint32_t *w, int nw,
                                              int32_t *status)
 {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -37,7 +42,7 @@ __global__ __launch_bounds__(T) void k_shinv(const uint32_t *v, int nv, int h, u
 }
 
 template <int T>
-__global__ __launch_bounds__(T) void k_divrem(const uint32_t *u, int nu, const uint32_t *v, int nv,
+__global__ __launch_bounds__(T) MP_OCCUPANCY void k_divrem(const uint32_t *u, int nu, const uint32_t *v, int nv,
                                               uint32_t *q, int nq, uint32_t *r, int32_t *status)
 {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -87,10 +92,16 @@ __global__ __launch_bounds__(1024) void k_ragged_prep(const mp_desc_t *desc, int
     }
 }
 
+__device__ __forceinline__ int64_t uniform64(int64_t x)
+{
+    const uint32_t lo = mp::uniform((uint32_t)x), hi = mp::uniform((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // persistent workgroups of one class: take the next instance of the class's
 // queue until it is empty
 template <int T>
-__global__ __launch_bounds__(T) void k_ragged(const uint32_t *up, const uint32_t *vp, const mp_desc_t *desc,
+__global__ __launch_bounds__(T) MP_OCCUPANCY void k_ragged(const uint32_t *up, const uint32_t *vp, const mp_desc_t *desc,
                                               uint32_t *qp, uint32_t *rp, int32_t *status, int32_t *ws, int cls,
                                               int count)
 {
@@ -100,12 +111,15 @@ __global__ __launch_bounds__(T) void k_ragged(const uint32_t *up, const uint32_t
         __syncthreads();
         if (threadIdx.x == 0) lds[mp::kCtlBcast + 2] = (uint32_t)atomicAdd(&ws[kClasses + cls], 1);
         __syncthreads();
-        const int idx = (int)lds[mp::kCtlBcast + 2];
+        // every value below is the same on all lanes: keep it in scalar registers
+        const int idx = mp::uniform((int)lds[mp::kCtlBcast + 2]);
         if (idx >= n) break;
-        const int j = ws[kWsHeader + (size_t)cls * count + idx];
-        const mp_desc_t d = desc[j];
-        mp::divrem_instance<T>(lds, up + d.u_off, d.nu, vp + d.v_off, d.nv, qp + d.q_off, d.nq, rp + d.r_off,
-                               status + j);
+        const int j = mp::uniform(ws[kWsHeader + (size_t)cls * count + idx]);
+        const mp_desc_t &d = desc[j];
+        const int64_t uo = uniform64(d.u_off), vo = uniform64(d.v_off), qo = uniform64(d.q_off),
+                      ro = uniform64(d.r_off);
+        const int nu = mp::uniform(d.nu), nv = mp::uniform(d.nv), nq = mp::uniform(d.nq);
+        mp::divrem_instance<T>(lds, up + uo, nu, vp + vo, nv, qp + qo, nq, rp + ro, status + j);
     }
 }
 
