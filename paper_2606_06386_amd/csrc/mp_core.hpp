@@ -38,6 +38,15 @@ constexpr int kCtlBcast = 240;   // 16 broadcast scalars
 constexpr int kCtlWords = 256;
 constexpr int kMaxStrips = 72;
 
+// barrier of the T threads working on an instance: the workgroup, or (T = 64)
+// a single wave, which needs no hardware barrier
+template <int T>
+MP_DEV void bar()
+{
+    if constexpr (T > kLanes) sync();
+    else wave_sync();
+}
+
 MP_DEV int round4(int x) { return (x + 3) & ~3; }
 MP_DEV int imin(int a, int b) { return a < b ? a : b; }
 MP_DEV int imax(int a, int b) { return a > b ? a : b; }
@@ -74,13 +83,16 @@ struct PowB {
     MP_DEV uint32_t operator()(int k) const { return k == e ? 1u : 0u; }
 };
 
-// strip carries of a product: carry e_s (64-bit) enters at column (s+1)*kStrip
+// strip carries of a product: carry e_s (64-bit) enters at column
+// (s+1)*kStrip - off
 struct StripCarries {
     const uint32_t *sc;
     int nstrips;
+    int off;
     MP_DEV uint32_t operator()(int k) const
     {
-        int s = (k / kStrip) - 1, o = k % kStrip;
+        const int kk = k + off;
+        int s = (kk / kStrip) - 1, o = kk % kStrip;
         if (s < 0 || s >= nstrips || o > 1) return 0u;
         return sc[2 * s + o];
     }
@@ -121,7 +133,7 @@ MP_DEV uint32_t wg_max(uint32_t *ctl, uint32_t x)
     constexpr int W = T / kLanes;
     x = wave_max(x);
     if (lane() == 0) ctl[kCtlRed + tid() / kLanes] = x;
-    sync();
+    bar<T>();
     uint32_t r = 0;
 #pragma unroll
     for (int w = 0; w < W; w++) {
@@ -142,7 +154,7 @@ MP_DEV void wg_max_n(uint32_t *ctl, uint32_t (&x)[N])
         const uint32_t m = wave_max(x[i]);
         if (lane() == 0) ctl[kCtlRed + 16 * i + w] = m;
     }
-    sync();
+    bar<T>();
 #pragma unroll
     for (int i = 0; i < N; i++) {
         uint32_t r = 0;
@@ -162,7 +174,7 @@ MP_DEV uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 template <int T, class F>
 MP_DEV int reduce_max(uint32_t *ctl, int n, const F &f)
 {
-    sync();
+    bar<T>();
     uint32_t m = 0;
     int k = tid();
     for (; k + 3 * T < n; k += 4 * T) {
@@ -251,7 +263,7 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
         ctl[kCtlScan + 2 * w] = s0 < X ? 1u : 0u;      // wave generates
         ctl[kCtlScan + 2 * w + 1] = (~P == 0) ? 1u : 0u;  // wave propagates
     }
-    sync();
+    bar<T>();
     // scan of the wave summaries: carry into this wave, and out of the number
     uint32_t cin_w = cin, cout = cin;
 #pragma unroll
@@ -291,7 +303,7 @@ template <int T>
 MP_DEV int read_prec(uint32_t *ctl, int off = 0)
 {
     constexpr int W = T / kLanes;
-    sync();
+    bar<T>();
     uint32_t r = 0;
 #pragma unroll
     for (int v = 0; v < W; v++) {
@@ -306,7 +318,7 @@ template <int T, class FX, class FY, class FO>
 MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
                        const FX &x, const FY &y, const FO &out)
 {
-    sync();
+    bar<T>();
     // odd chunk length: lanes then touch LDS with an odd word stride (no bank conflicts)
     const int C = ((n + T - 1) / T) | 1;
     if (C == 1) return addsub_chunk<T, 1>(ctl, n, C, sub, cin, x, y, out);
@@ -320,7 +332,7 @@ MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
 template <int T, class FS>
 MP_DEV void copy(uint32_t *dst, int n, int clear, const FS &src)
 {
-    sync();
+    bar<T>();
     const int e = imax(n, clear);
     int k = tid();
     for (; k + 3 * T < e; k += 4 * T) {
@@ -339,10 +351,11 @@ MP_DEV void copy(uint32_t *dst, int n, int clear, const FS &src)
 // Turns the 96-bit column sums lo/hi of strip s (first column K0; lane l
 // holds columns K0 + 4l .. K0 + 4l + 3) into limbs: lane-local carry, the
 // neighbour's carry by shuffle, then a carry-lookahead over the wave from
-// ballots.  The limbs below ncols go to p; the carry leaving the strip goes to
-// the strip carry slot s (added to the next strip by the final addsub).
+// ballots.  The limbs of columns in [c0, ncols) go to p (c0 a multiple of 4);
+// the carry leaving the strip goes to the strip carry slot s (added to the
+// next strip by the final addsub).
 MP_DEV void strip_resolve(uint32_t *ctl, int s, int K0, const uint64_t (&lo)[4], const uint32_t (&hi)[4],
-                          uint32_t *p, int ncols)
+                          uint32_t *p, int c0, int ncols)
 {
     const int l = lane();
     const int k0 = K0 + l * kRCol;
@@ -376,12 +389,14 @@ MP_DEV void strip_resolve(uint32_t *ctl, int s, int K0, const uint64_t (&lo)[4],
         z[r] += ci;
         ci &= (z[r] == 0u) ? 1u : 0u;
     }
-    if (k0 + 3 < ncols) {
-        store4(p + k0, z[0], z[1], z[2], z[3]);
-    } else {
+    if (k0 >= c0) {
+        if (k0 + 3 < ncols) {
+            store4(p + k0, z[0], z[1], z[2], z[3]);
+        } else {
 #pragma unroll
-        for (int r = 0; r < 4; r++)
-            if (k0 + r < ncols) p[k0 + r] = z[r];
+            for (int r = 0; r < 4; r++)
+                if (k0 + r < ncols) p[k0 + r] = z[r];
+        }
     }
     if (l == kLanes - 1) {
         const uint64_t e = c + (sum < X ? 1u : 0u);
@@ -391,15 +406,26 @@ MP_DEV void strip_resolve(uint32_t *ctl, int s, int K0, const uint64_t (&lo)[4],
 }
 
 
-// p[c0, ncols) += the strip carries (strip s's carry enters at column
-// c0 + (s+1) kStrip), mod B^(ncols - c0); returns the precision as mul's
+// p[c0, ncols) += the strip carries (strip s, based at column base, passes
+// its carry to column base + (s+1) kStrip), mod B^(ncols - c0); returns the
+// precision as mul's
 template <int T>
-MP_DEV int add_strip_carries(uint32_t *ctl, uint32_t *p, int c0, int ncols, int nstrips)
+MP_DEV int add_strip_carries(uint32_t *ctl, uint32_t *p, int c0, int ncols, int nstrips, int base)
 {
     const int n = ncols - c0;
-    addsub<T>(ctl, n, false, 0u, Span{p + c0, 0, n}, StripCarries{ctl + kCtlStrip, nstrips}, Store{p + c0, 0, n});
+    addsub<T>(ctl, n, false, 0u, Span{p + c0, 0, n}, StripCarries{ctl + kCtlStrip, nstrips, c0 - base},
+              Store{p + c0, 0, n});
     const int e = read_prec<T>(ctl);
     return e ? e + c0 : 0;
+}
+
+// First column of the lowest strip.  A product kept only mod B^ncols (c0 = 0,
+// ncols short of the full width) ends its top strip at ncols (rounded up to 8
+// limbs) so that the partial strip is the lowest one, which has the fewest
+// products; other products start at c0, leaving the cheap top strip partial.
+MP_DEV int strip_base(int c0, int ncols, int nfull, int nstrips)
+{
+    return (c0 == 0 && ncols < nfull) ? ((ncols + 7) & ~7) - nstrips * kStrip : c0;
 }
 
 // p[c0, ncols) = the columns c0 .. ncols-1 of a * b, ncols <= na + nb (with
@@ -426,15 +452,16 @@ MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
                const uint32_t *a, int na, const uint32_t *bw, int nb, int c0 = 0)
 {
     constexpr int W = T / kLanes;
-    sync();
+    bar<T>();
     if (na == 0 || nb == 0 || ncols <= c0) {
         for (int k = c0 + tid(); k < ncols; k += T) p[k] = 0u;
         return 0;
     }
     const int nstrips = (ncols - c0 + kStrip - 1) / kStrip;
+    const int base = strip_base(c0, ncols, na + nb, nstrips);
     const int w = uniform(tid() / kLanes), l = lane();
     for (int s = w; s < nstrips; s += W) {
-        const int K0 = c0 + s * kStrip, k0 = K0 + l * kRCol;
+        const int K0 = base + s * kStrip, k0 = K0 + l * kRCol;
         const int ilo = imax(0, K0 - nb + 1) & ~3;
         const int ihi = imin(na, imin(K0 + kStrip, ncols));
         uint64_t lo[4] = {0, 0, 0, 0};
@@ -481,9 +508,9 @@ MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
                 }
             }
         }
-        strip_resolve(ctl, s, K0, lo, hi, p, ncols);
+        strip_resolve(ctl, s, K0, lo, hi, p, c0, ncols);
     }
-    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips);
+    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base);
 }
 
 // ---------------------------------------------------- matrix-core product
@@ -542,11 +569,11 @@ template <int T, class FY, class FX>
 MP_DEV void mfma_operands(uint32_t *ctl, const FY &y, int ny, uint32_t *yb, int yclear,
                           const FX &x, int nx, uint32_t *xr)
 {
-    sync();
+    bar<T>();
     for (int k = ny + 1 + tid(); k < yclear; k += T) yb[k] = 0u;
     addsub<T>(ctl, ny + 1, false, 0u, y, Bal80{ny}, StoreBal{yb, ny});
     addsub<T>(ctl, nx + 1, false, 0u, x, Bal80{nx}, StoreBalRev{xr, nx});
-    sync();
+    bar<T>();
     for (int k = tid(); k < 2 * kXPad; k += T) {
         if (k < kXPad) xr[k - kXPad] = 0u;
         else xr[nx + 1 + k - kXPad] = 0u;
@@ -564,16 +591,17 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
                     const uint32_t *xr, int nx, int c0 = 0)
 {
     constexpr int W = T / kLanes;
-    sync();
+    bar<T>();
     if (ncols <= c0) return 0;
     const int nstrips = (ncols - c0 + kStrip - 1) / kStrip;
+    const int base = strip_base(c0, ncols, nx + ny, nstrips);
     const int w = uniform(tid() / kLanes), l = lane();
     const int t = l & 31, h = l >> 5;
     const int nyblk = (ny + 1 + 7) >> 3;          // 32-byte blocks of the long digits
     const int R0 = 4 * (nx + 1) - 1;              // reversed byte x holds digit R0 - x
     const int dmax = (4 * (nx + 1) + 30) >> 5;    // last diagonal touching the short digits
     for (int s = w; s < nstrips; s += W) {
-        const int S0 = 32 * s + (c0 >> 3);        // first 8-limb block of the strip
+        const int S0 = 32 * s + (base >> 3);      // first 8-limb block of the strip
         const int dlo = imax(0, S0 - nyblk + 1), dhi = imin(dmax, S0 + 31);
         MfmaAcc acc0 = mfma_zero(), acc1 = mfma_zero();
         for (int d = dlo; d <= dhi; d += 2) {
@@ -594,15 +622,15 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
             }
         }
         const MfmaAcc acc = mfma_add(acc0, acc1);
-        // limb columns 8t + 2q + h of the strip, biased to be non-negative: column c0
-        // gets 2^56, every other column 2^56 - 2^24 (the biases telescope to
+        // limb columns 8t + 2q + h of the strip, biased to be non-negative: column
+        // base gets 2^56, every other column 2^56 - 2^24 (the biases telescope to
         // 2^24 B^ncols, i.e. to 0 mod B^ncols)
         uint32_t tl[4], th[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             const int64_t m = (int64_t)mfma_get(acc, 4 * q) + (int64_t)mfma_get(acc, 4 * q + 1) * 256 +
                               (int64_t)mfma_get(acc, 4 * q + 2) * 65536 + (int64_t)mfma_get(acc, 4 * q + 3) * 16777216;
-            const int col = s * kStrip + 8 * t + 2 * q + h;   // relative to c0
+            const int col = s * kStrip + 8 * t + 2 * q + h;   // relative to base
             const uint64_t v = (uint64_t)(m + (col == 0 ? ((int64_t)1 << 56) : ((int64_t)1 << 56) - ((int64_t)1 << 24)));
             tl[q] = (uint32_t)v;
             th[q] = (uint32_t)(v >> 32);
@@ -619,9 +647,9 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
             const uint32_t bl = shfl(tl[2 + (j >> 1)], src), bh = shfl(th[2 + (j >> 1)], src);
             lo[j] = par ? (((uint64_t)bh << 32) | bl) : (((uint64_t)ah << 32) | al);
         }
-        strip_resolve(ctl, s, c0 + s * kStrip, lo, hi, p, ncols);
+        strip_resolve(ctl, s, base + s * kStrip, lo, hi, p, c0, ncols);
     }
-    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips);
+    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base);
 }
 
 // --------------------------------------------------------- short division
@@ -635,7 +663,7 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
 template <int T, class FD, class FO>
 MP_DEV uint32_t shortdiv(uint32_t *ctl, uint32_t *scratch, int n, const FD &d, uint32_t dv, const FO &qout)
 {
-    sync();
+    bar<T>();
     const int C = imax((n + T - 1) / T, imin(n, 64));
     const int nch = (n + C - 1) / C;
     const int t = tid(), k0 = t * C;
@@ -648,7 +676,7 @@ MP_DEV uint32_t shortdiv(uint32_t *ctl, uint32_t *scratch, int n, const FD &d, u
         }
         scratch[t] = (uint32_t)r;
     }
-    sync();
+    bar<T>();
     if (t == 0) {
         uint64_t beta = 1;
         for (int j = 0; j < C; j++) beta = (beta << 32) % dv;   // B^C mod dv
@@ -659,7 +687,7 @@ MP_DEV uint32_t shortdiv(uint32_t *ctl, uint32_t *scratch, int n, const FD &d, u
         }
         ctl[kCtlBcast] = (uint32_t)R;
     }
-    sync();
+    bar<T>();
     if (t < nch) {
         uint64_t R = scratch[T + t];
         for (int j = C - 1; j >= 0; j--) {

@@ -152,20 +152,105 @@ MP_DEV int ceil_log2(int x)   // x >= 1
 
 // ------------------------------------------------------- Alg. 1 Refine
 
-// Initial approximation and the Refine loop for B^k <= v < B^(k+1), k >= 1,
-// h - k >= 1, B < v <= B^h / 2, v not a power of B.  v is in V (k+1 limbs).
-// On return the shifted inverse is the limbs of W above `shf`; W's nonzero
-// limbs lie inside [0, we) and nw = prec(W).  Returns false if a capacity
-// guard trips or a Step result turns negative (never expected).
+// Iteration i of the Refine loop (Alg. 1): PowDiff, then Step, updating the
+// iterate W (nonzero limbs inside [0, we), precision nw) and l.  Run by T
+// threads (the workgroup, or one wave for the small early iterations).
 template <int T>
-MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, int &we, int &nw, int &shf,
-                   int &sbext)
+MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, int i, int &l, int &we,
+                        int &nw, int &sbext)
 {
     uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
     uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP, *XR = lds + pl.offR;
     const int g = 2, d = h - k;
+    const int m = imin(d + 1 - l, l);
+    const int s = imax(0, k - 2 * l + 1 - g);
+    const int H = k + l + m - s + g;
+    const uint32_t *vp = V + s;          // divisor prefix shift_{-s}(v)
+    const int nvp = k + 1 - s;
+    const int hp = H - m, lp = l - g;   // PowDiff(v', w, H - m, l - g)
+    const int L = nvp + nw - lp + 1;
+    bool sign;
+    int nx;
+    if (L >= hp) {                      // full product, compare with B^hp
+        const int np0 = nvp + nw;
+        if (np0 > pl.capP) return false;
+        const int np = product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR);
+        if (np <= hp) {                 // P < B^hp: x = B^hp - P
+            if (hp > pl.capX) return false;
+            sign = true;
+            addsub<T>(ctl, hp, true, 0u, Zero{}, Span{P, 0, np}, Store{X, 0, hp});
+        } else {                        // x = P - B^hp
+            if (np > pl.capX) return false;
+            sign = false;
+            addsub<T>(ctl, np, true, 0u, Span{P, 0, np}, PowB{hp}, Store{X, 0, np});
+        }
+        nx = read_prec<T>(ctl);
+    } else {                            // close product: P = v'w mod B^L
+        if (L > pl.capP || L > pl.capX) return false;
+        const int np = product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR);
+        if (np == 0) {                  // v'w = B^hp exactly
+            sign = true;
+            nx = 0;
+        } else if (np < L) {            // top limb 0: v'w = B^hp + P
+            sign = false;
+            nx = np;
+            copy<T>(X, np, 0, Span{P, 0, np});
+        } else {                        // v'w = B^hp - (B^L - P)
+            sign = true;
+            addsub<T>(ctl, L, true, 0u, Zero{}, Span{P, 0, L}, Store{X, 0, L});
+            nx = read_prec<T>(ctl);
+        }
+    }
+    // Step: res = shift_m(w) +- shift_{2m-H}(w x); then w = shift_{-post}(res).
+    // Only the columns of w x from cs = sh - 2 (rounded down to a multiple
+    // of 8) up are formed: the columns below change the shifted product by
+    // less than one unit of the iterate's last guard limb, and the sticky
+    // bit of the negative branch is taken from the formed columns below sh.
+    // The matrix-core digits can make the dropped part negative, so the
+    // formed sum T may exceed w x: one more column holds T < 2 B^(nw+nx),
+    // and nw + nx >= sh + 2 keeps T > 0 (w x >= B^(nw+nx-2) exceeds the
+    // dropped part).
+    const int sh = H - 2 * m;
+    const int post = i < 2 ? m : 1;
+    int nt = 0, cs = 0;
+    if (nx) {
+        nt = nw + nx;
+        cs = nt >= sh + 2 ? imax(sh - 2, 0) & ~7 : 0;
+        if (cs) nt += 1;
+        if (nt > pl.capP) return false;
+        product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, cs);
+    }
+    uint32_t sticky = 0;
+    if (!sign && nt > cs) {
+        const int top = imin(sh, nt);
+        sticky = reduce_max<T>(ctl, top - cs, [&](int j) -> uint32_t { return P[cs + j] ? 1u : 0u; });
+    }
+    const int nres = imax(nw + m, nt - sh) + 1;
+    if (nres - post > pl.capW) return false;
+    const uint32_t co = addsub<T>(ctl, nres, !sign, sticky, Span{W, m, nw}, Span{P, -sh, imax(nt, 0)},
+                                  Store{W, post, pl.capW});
+    if (!sign && co) return false;
+    we = nres - post;
+    nw = read_prec<T>(ctl, post);
+    if (i >= 2) l = l + m - 1;
+    return true;
+}
+
+// Initial approximation and the Refine loop for B^k <= v < B^(k+1), k >= 1,
+// h - k >= 1, B < v <= B^h / 2, v not a power of B.  v is in V (k+1 limbs).
+// On return the shifted inverse is the limbs of W above `shf`; W's nonzero
+// limbs lie inside [0, we) and nw = prec(W).  Returns false if a capacity
+// guard trips or a Step result turns negative (never expected).  The early
+// iterations, whose operands are all shorter than kMfmaMin limbs, run on the
+// first wave alone (no workgroup barriers) while the others wait.
+template <int T>
+MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, int &we, int &nw, int &shf,
+                   int &sbext)
+{
+    uint32_t *V = lds + pl.offV, *W = lds + pl.offW;
+    const int g = 2, d = h - k;
     // w = shift_g(floor(B^3 / V)), V = v_{k-1} + v_k B; w0 <= B^2 has 3 limbs
-    sync();
+    bar<T>();
     if (tid() == 0) {
         const uint64_t Vt = ((uint64_t)V[k] << 32) | V[k - 1];
         const unsigned __int128 w0 = (((unsigned __int128)1) << 96) / Vt;
@@ -176,84 +261,40 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
         W[4] = (uint32_t)(w0 >> 64);
         ctl[kCtlBcast + 1] = W[4] ? 5u : W[3] ? 4u : 3u;
     }
-    sync();
+    bar<T>();
     nw = (int)uniform(ctl[kCtlBcast + 1]);
     we = 5;
     int l = 2;
     const int iters = 2 + (d - 1 <= 1 ? 0 : ceil_log2(d - 1));
-    for (int i = 0; i < iters; i++) {
-        const int m = imin(d + 1 - l, l);
-        const int s = imax(0, k - 2 * l + 1 - g);
-        const int H = k + l + m - s + g;
-        const uint32_t *vp = V + s;          // divisor prefix shift_{-s}(v)
-        const int nvp = k + 1 - s;
-        const int hp = H - m, lp = l - g;   // PowDiff(v', w, H - m, l - g)
-        const int L = nvp + nw - lp + 1;
-        bool sign;
-        int nx;
-        if (L >= hp) {                      // full product, compare with B^hp
-            const int np0 = nvp + nw;
-            if (np0 > pl.capP) return false;
-            const int np = product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR);
-            if (np <= hp) {                 // P < B^hp: x = B^hp - P
-                if (hp > pl.capX) return false;
-                sign = true;
-                addsub<T>(ctl, hp, true, 0u, Zero{}, Span{P, 0, np}, Store{X, 0, hp});
-            } else {                        // x = P - B^hp
-                if (np > pl.capX) return false;
-                sign = false;
-                addsub<T>(ctl, np, true, 0u, Span{P, 0, np}, PowB{hp}, Store{X, 0, np});
+    int i = 0;
+    if constexpr (T > kLanes) {
+        int nsmall = 0;                       // iterations with an iterate of l + g + 1 < kMfmaMin limbs
+        for (int ll = 2; nsmall < iters && ll + g + 1 < kMfmaMin; nsmall++)
+            if (nsmall >= 2) ll = ll + imin(d + 1 - ll, ll) - 1;
+        if (nsmall > 0) {
+            if (tid() < kLanes) {
+                bool ok = true;
+                int l1 = l, we1 = we, nw1 = nw, sb1 = sbext;
+                for (int j = 0; j < nsmall && ok; j++) ok = refine_iter<kLanes>(ctl, pl, lds, h, k, j, l1, we1, nw1, sb1);
+                if (tid() == 0) {
+                    ctl[kCtlBcast + 3] = ok ? 1u : 0u;
+                    ctl[kCtlBcast + 4] = (uint32_t)l1;
+                    ctl[kCtlBcast + 5] = (uint32_t)we1;
+                    ctl[kCtlBcast + 6] = (uint32_t)nw1;
+                    ctl[kCtlBcast + 7] = (uint32_t)sb1;
+                }
             }
-            nx = read_prec<T>(ctl);
-        } else {                            // close product: P = v'w mod B^L
-            if (L > pl.capP || L > pl.capX) return false;
-            const int np = product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR);
-            if (np == 0) {                  // v'w = B^hp exactly
-                sign = true;
-                nx = 0;
-            } else if (np < L) {            // top limb 0: v'w = B^hp + P
-                sign = false;
-                nx = np;
-                copy<T>(X, np, 0, Span{P, 0, np});
-            } else {                        // v'w = B^hp - (B^L - P)
-                sign = true;
-                addsub<T>(ctl, L, true, 0u, Zero{}, Span{P, 0, L}, Store{X, 0, L});
-                nx = read_prec<T>(ctl);
-            }
+            sync();
+            if (!uniform(ctl[kCtlBcast + 3])) return false;
+            l = (int)uniform(ctl[kCtlBcast + 4]);
+            we = (int)uniform(ctl[kCtlBcast + 5]);
+            nw = (int)uniform(ctl[kCtlBcast + 6]);
+            sbext = (int)uniform(ctl[kCtlBcast + 7]);
+            i = nsmall;
         }
-        // Step: res = shift_m(w) +- shift_{2m-H}(w x); then w = shift_{-post}(res).
-        // Only the columns of w x from cs = sh - 2 (rounded down to a multiple
-        // of 8) up are formed: the columns below change the shifted product by
-        // less than one unit of the iterate's last guard limb, and the sticky
-        // bit of the negative branch is taken from the formed columns below sh.
-        // The matrix-core digits can make the dropped part negative, so the
-        // formed sum T may exceed w x: one more column holds T < 2 B^(nw+nx),
-        // and nw + nx >= sh + 2 keeps T > 0 (w x >= B^(nw+nx-2) exceeds the
-        // dropped part).
-        const int sh = H - 2 * m;
-        const int post = i < 2 ? m : 1;
-        int nt = 0, cs = 0;
-        if (nx) {
-            nt = nw + nx;
-            cs = nt >= sh + 2 ? imax(sh - 2, 0) & ~7 : 0;
-            if (cs) nt += 1;
-            if (nt > pl.capP) return false;
-            product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, cs);
-        }
-        uint32_t sticky = 0;
-        if (!sign && nt > cs) {
-            const int top = imin(sh, nt);
-            sticky = reduce_max<T>(ctl, top - cs, [&](int j) -> uint32_t { return P[cs + j] ? 1u : 0u; });
-        }
-        const int nres = imax(nw + m, nt - sh) + 1;
-        if (nres - post > pl.capW) return false;
-        const uint32_t co = addsub<T>(ctl, nres, !sign, sticky, Span{W, m, nw}, Span{P, -sh, imax(nt, 0)},
-                                      Store{W, post, pl.capW});
-        if (!sign && co) return false;
-        we = nres - post;
-        nw = read_prec<T>(ctl, post);
-        if (i >= 2) l = l + m - 1;
     }
+    for (; i < iters; i++)
+        if (!refine_iter<T>(ctl, pl, lds, h, k, i, l, we, nw, sbext)) return false;
     shf = d < 2 ? 4 - d : 2;
     return true;
 }
@@ -282,7 +323,7 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
         np = mul<T>(ctl, P, na + nb, A, nlo, SB, nhi);
     }
     (void)np;
-    sync();
+    bar<T>();
     for (int i = tid(); i < na + nb; i += T) c[i] = P[i];
 }
 
@@ -349,7 +390,7 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
             int adj = 0;
             bool good = true;
             for (int it = 0; good; it++) {         // D < 0: s too large
-                sync();
+                bar<T>();
                 if (!(R[Lr - 1] >> 31)) break;
                 if (it == 4) { good = false; break; }
                 addsub<T>(ctl, Lr, false, 0u, Span{R, 0, Lr}, Span{V, 0, k + 1}, Store{R, 0, Lr});
@@ -374,7 +415,7 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
     }
     if (st == kInstOk && !ok) st = kInstQWidth;
     if (st != kInstOk) {
-        sync();
+        bar<T>();
         store_zero<T>(w, nw);
     }
     if (status && tid() == 0) *status = st;
@@ -391,7 +432,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     bool ok = true;
     // one pass over u and v: prec(u), prec(v), and the lowest nonzero limb of v
     uint32_t red[3] = {0u, 0u, 0u};
-    sync();
+    bar<T>();
     {
         // four limbs of u and of v per thread and step, all read before use
         const int nm = nu > nv ? nu : nv;
@@ -451,7 +492,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         int we = 0, nw = 0, shf = 0, sbext = 0;
         bool good = true;
         if (k == h - 1 && (vk > 0x80000000u || (vk == 0x80000000u && !lowz))) {
-            sync();                               // 2v > B^h: shinv = 1
+            bar<T>();                               // 2v > B^h: shinv = 1
             if (tid() == 0) W[0] = 1u;
             we = 1;
             nw = 1;
@@ -487,7 +528,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
                 addsub<T>(ctl, rl, true, 0u, Ug, Span{P, 0, rl}, Store{R, 0, rl});
                 // r0 < 0 (top bit of the signed value): add v until it is not
                 for (int it = 0; good; it++) {
-                    sync();
+                    bar<T>();
                     if (!(R[rl - 1] >> 31)) break;
                     if (it == 4) { good = false; break; }
                     addsub<T>(ctl, rl, false, 0u, Span{R, 0, rl}, Span{V, 0, k + 1}, Store{R, 0, rl});
@@ -519,7 +560,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     }
     if (st == kInstOk && !ok) st = kInstQWidth;
     if (st != kInstOk) {
-        sync();
+        bar<T>();
         store_zero<T>(q, nq);
         store_zero<T>(r, nv);
     }

@@ -18,6 +18,10 @@ constexpr int kLanes = 64;  // CDNA wavefront width
 MP_DEV int tid() { return (int)threadIdx.x; }
 MP_DEV int lane() { return (int)(threadIdx.x & (kLanes - 1)); }
 MP_DEV void sync() { __syncthreads(); }
+// orders this wave's LDS accesses before and after it (a wave runs in
+// lockstep and the LDS serves one wave's requests in order; only the
+// compiler must not move accesses across)
+MP_DEV void wave_sync() { asm volatile("" ::: "memory"); }
 MP_DEV uint64_t ballot(bool p) { return __ballot(p); }
 
 // value held by lane-1 (lane 0 receives 0)
