@@ -408,13 +408,14 @@ MP_DEV void strip_resolve(uint32_t *ctl, int s, int K0, const uint64_t (&lo)[4],
 
 // p[c0, ncols) += the strip carries (strip s, based at column base, passes
 // its carry to column base + (s+1) kStrip), mod B^(ncols - c0); returns the
-// precision as mul's
+// precision as mul's (or -1 without want_prec, saving a barrier)
 template <int T>
-MP_DEV int add_strip_carries(uint32_t *ctl, uint32_t *p, int c0, int ncols, int nstrips, int base)
+MP_DEV int add_strip_carries(uint32_t *ctl, uint32_t *p, int c0, int ncols, int nstrips, int base, bool want_prec)
 {
     const int n = ncols - c0;
     addsub<T>(ctl, n, false, 0u, Span{p + c0, 0, n}, StripCarries{ctl + kCtlStrip, nstrips, c0 - base},
               Store{p + c0, 0, n});
+    if (!want_prec) return -1;
     const int e = read_prec<T>(ctl);
     return e ? e + c0 : 0;
 }
@@ -449,7 +450,7 @@ MP_DEV int strip_base(int c0, int ncols, int nfull, int nstrips)
 // ballot); the carry leaving each strip is added by one final addsub pass.
 template <int T>
 MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
-               const uint32_t *a, int na, const uint32_t *bw, int nb, int c0 = 0)
+               const uint32_t *a, int na, const uint32_t *bw, int nb, int c0 = 0, bool want_prec = true)
 {
     constexpr int W = T / kLanes;
     bar<T>();
@@ -510,7 +511,7 @@ MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
         }
         strip_resolve(ctl, s, K0, lo, hi, p, c0, ncols);
     }
-    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base);
+    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base, want_prec);
 }
 
 // ---------------------------------------------------- matrix-core product
@@ -573,7 +574,8 @@ MP_DEV void mfma_operands(uint32_t *ctl, const FY &y, int ny, uint32_t *yb, int 
     for (int k = ny + 1 + tid(); k < yclear; k += T) yb[k] = 0u;
     addsub<T>(ctl, ny + 1, false, 0u, y, Bal80{ny}, StoreBal{yb, ny});
     addsub<T>(ctl, nx + 1, false, 0u, x, Bal80{nx}, StoreBalRev{xr, nx});
-    bar<T>();
+    // every read of x happened before addsub's internal barrier, and the pads
+    // are disjoint from the digits written: no barrier needed here
     for (int k = tid(); k < 2 * kXPad; k += T) {
         if (k < kXPad) xr[k - kXPad] = 0u;
         else xr[nx + 1 + k - kXPad] = 0u;
@@ -588,7 +590,7 @@ MP_DEV void mfma_operands(uint32_t *ctl, const FY &y, int ny, uint32_t *yb, int 
 // from the limb-product sum by less than 2^16 c0 B^c0 in either direction.
 template <int T>
 MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, int ny,
-                    const uint32_t *xr, int nx, int c0 = 0)
+                    const uint32_t *xr, int nx, int c0 = 0, bool want_prec = true)
 {
     constexpr int W = T / kLanes;
     bar<T>();
@@ -602,24 +604,31 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
     const int dmax = (4 * (nx + 1) + 30) >> 5;    // last diagonal touching the short digits
     for (int s = w; s < nstrips; s += W) {
         const int S0 = 32 * s + (base >> 3);      // first 8-limb block of the strip
-        const int dlo = imax(0, S0 - nyblk + 1), dhi = imin(dmax, S0 + 31);
+        const int dlo = uniform(imax(0, S0 - nyblk + 1)), dhi = uniform(imin(dmax, S0 + 31));
         MfmaAcc acc0 = mfma_zero(), acc1 = mfma_zero();
-        for (int d = dlo; d <= dhi; d += 2) {
-#pragma unroll
-            for (int e = 0; e < 2; e++) {
-                const int dd = d + e;
-                if (e == 1 && dd > dhi) break;
-                const int o = R0 - 32 * dd - t + 16 * h;   // first reversed byte of X_d row t, half h
-                const int wq = o >> 2;
-                const uint32_t sft = (uint32_t)o & 3u;
-                const uint32_t *xp = xr + wq;
-                const uint32_t q0 = xp[0], q1 = xp[1], q2 = xp[2], q3 = xp[3], q4 = xp[4];
-                const Limb4 yv = load4(yb + 8 * (S0 + t - dd) + 4 * h);
-                const uint32_t x0 = alignbyte(q1, q0, sft), x1 = alignbyte(q2, q1, sft);
-                const uint32_t x2 = alignbyte(q3, q2, sft), x3 = alignbyte(q4, q3, sft);
-                if (e == 0) acc0 = mfma_i8(acc0, x0, x1, x2, x3, yv.x, yv.y, yv.z, yv.w);
-                else acc1 = mfma_i8(acc1, x0, x1, x2, x3, yv.x, yv.y, yv.z, yv.w);
-            }
+        // Row t, half h of X_d starts at reversed byte R0 - 32 d - t + 16 h: its
+        // word address drops by 8 per diagonal and its byte shift is the same for
+        // every d.  Y_d's block address drops by 8 limbs per diagonal.
+        const int o0 = R0 - 32 * dlo - t + 16 * h;
+        const uint32_t sft = (uint32_t)o0 & 3u;
+        const uint32_t *xp = xr + (o0 >> 2);
+        const uint32_t *yp = yb + 8 * (S0 + t - dlo) + 4 * h;
+        int d = dlo;
+        for (; d + 1 <= dhi; d += 2, xp -= 16, yp -= 16) {
+            // all reads of the pair of diagonals first, then its two products
+            const uint32_t a0 = xp[0], a1 = xp[1], a2 = xp[2], a3 = xp[3], a4 = xp[4];
+            const uint32_t b0 = xp[-8], b1 = xp[-7], b2 = xp[-6], b3 = xp[-5], b4 = xp[-4];
+            const Limb4 y0 = load4(yp), y1 = load4(yp - 8);
+            acc0 = mfma_i8(acc0, alignbyte(a1, a0, sft), alignbyte(a2, a1, sft), alignbyte(a3, a2, sft),
+                           alignbyte(a4, a3, sft), y0.x, y0.y, y0.z, y0.w);
+            acc1 = mfma_i8(acc1, alignbyte(b1, b0, sft), alignbyte(b2, b1, sft), alignbyte(b3, b2, sft),
+                           alignbyte(b4, b3, sft), y1.x, y1.y, y1.z, y1.w);
+        }
+        if (d <= dhi) {
+            const uint32_t a0 = xp[0], a1 = xp[1], a2 = xp[2], a3 = xp[3], a4 = xp[4];
+            const Limb4 y0 = load4(yp);
+            acc0 = mfma_i8(acc0, alignbyte(a1, a0, sft), alignbyte(a2, a1, sft), alignbyte(a3, a2, sft),
+                           alignbyte(a4, a3, sft), y0.x, y0.y, y0.z, y0.w);
         }
         const MfmaAcc acc = mfma_add(acc0, acc1);
         // limb columns 8t + 2q + h of the strip, biased to be non-negative: column
@@ -649,7 +658,7 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
         }
         strip_resolve(ctl, s, base + s * kStrip, lo, hi, p, c0, ncols);
     }
-    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base);
+    return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base, want_prec);
 }
 
 // --------------------------------------------------------- short division

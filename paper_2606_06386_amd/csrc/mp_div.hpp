@@ -95,26 +95,27 @@ MP_HD int mul_lds_words(int na, int nb)
 template <int T, class FL, class FS>
 MP_DEV int product_views(uint32_t *ctl, uint32_t *p, int ncols, const FL &lng, int nl, const uint32_t *lng_lds,
                          const FS &sht, int ns, const uint32_t *sht_lds, uint32_t *sb, int &sbext,
-                         uint32_t *xr, int xrcap, int c0 = 0)
+                         uint32_t *xr, int xrcap, int c0 = 0, bool want_prec = true)
 {
     if (ns >= kMfmaMin && ns + 1 <= xrcap) {
         mfma_operands<T>(ctl, lng, nl, sb, sbext, sht, ns, xr);
         sbext = nl + 1;
-        return mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0);
+        return mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0, want_prec);
     }
     copy<T>(sb, nl, sbext, lng);
     sbext = nl;
-    return mul<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0);
+    return mul<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0, want_prec);
 }
 
 template <int T>
 MP_DEV int product(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *x, int nx,
-                   const uint32_t *y, int ny, uint32_t *sb, int &sbext, uint32_t *xr, int xrcap, int c0 = 0)
+                   const uint32_t *y, int ny, uint32_t *sb, int &sbext, uint32_t *xr, int xrcap, int c0 = 0,
+                   bool want_prec = true)
 {
     const uint32_t *sht = nx >= ny ? y : x, *lng = nx >= ny ? x : y;
     const int ns = nx >= ny ? ny : nx, nl = nx >= ny ? nx : ny;
     return product_views<T>(ctl, p, ncols, Span{lng, 0, nl}, nl, lng, Span{sht, 0, ns}, ns, sht, sb, sbext,
-                            xr, xrcap, c0);
+                            xr, xrcap, c0, want_prec);
 }
 
 // dst[0, n) = src limbs [0, e) zero-padded, where e = prec(src) must be <= n;
@@ -218,7 +219,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int
         cs = nt >= sh + 2 ? imax(sh - 2, 0) & ~7 : 0;
         if (cs) nt += 1;
         if (nt > pl.capP) return false;
-        product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, cs);
+        product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, cs, false);
     }
     uint32_t sticky = 0;
     if (!sign && nt > cs) {
@@ -316,11 +317,11 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
     if (nlo >= kMfmaMin) {
         copy<T>(SBbase, 0, 2 * kPad + r4(nhi + 1), Zero{});
         mfma_operands<T>(ctl, Span{lng, 0, nhi}, nhi, SB, 0, Span{sht, 0, nlo}, nlo, A);
-        np = mul_mfma<T>(ctl, P, na + nb, SB, nhi, A, nlo);
+        np = mul_mfma<T>(ctl, P, na + nb, SB, nhi, A, nlo, 0, false);
     } else {
         copy<T>(A, nlo, r4(nlo) + 4, Span{sht, 0, nlo});
         copy<T>(SBbase, kPad + nhi, 2 * kPad + r4(nhi), Span{lng, kPad, nhi});
-        np = mul<T>(ctl, P, na + nb, A, nlo, SB, nhi);
+        np = mul<T>(ctl, P, na + nb, A, nlo, SB, nhi, 0, false);
     }
     (void)np;
     bar<T>();
@@ -384,7 +385,7 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
             const int full = k + 1 + ns;
             const int Lr = d >= 3 ? k + 3 : imax(full, h + 1) + 1;
             const int pc = imin(Lr, full);
-            product<T>(ctl, P, pc, V, k + 1, S, ns, SB, sbext, XR, pl.capR);
+            product<T>(ctl, P, pc, V, k + 1, S, ns, SB, sbext, XR, pl.capR, 0, false);
             addsub<T>(ctl, Lr, true, 0u, PowB{h}, Span{P, 0, pc}, Store{X, 0, Lr});
             uint32_t *R = X, *R2 = P;
             int adj = 0;
@@ -522,7 +523,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
                 // (k+2)-limb number and only the low k+2 limbs of m = v q0 are
                 // needed.  The loops below allow one more step each way.
                 const int rl = k + 2;
-                product<T>(ctl, P, rl, W, nq0, V, k + 1, SB, sbext, XR, pl.capR);
+                product<T>(ctl, P, rl, W, nq0, V, k + 1, SB, sbext, XR, pl.capR, 0, false);
                 uint32_t *R = SB, *R2 = X;
                 int delta = 0;
                 addsub<T>(ctl, rl, true, 0u, Ug, Span{P, 0, rl}, Store{R, 0, rl});
