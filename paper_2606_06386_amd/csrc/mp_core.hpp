@@ -132,6 +132,7 @@ MP_DEV uint32_t wg_max(uint32_t *ctl, uint32_t x)
 {
     constexpr int W = T / kLanes;
     x = wave_max(x);
+    if constexpr (W == 1) return uniform(x);
     if (lane() == 0) ctl[kCtlRed + tid() / kLanes] = x;
     bar<T>();
     uint32_t r = 0;
@@ -259,17 +260,22 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
     const uint64_t G = ballot(c != 0), P = ballot(prop), X = G | P;
     const uint64_t s0 = X + G;
     const int w = uniform(tid() / kLanes);
-    if (lane() == 0) {
-        ctl[kCtlScan + 2 * w] = s0 < X ? 1u : 0u;      // wave generates
-        ctl[kCtlScan + 2 * w + 1] = (~P == 0) ? 1u : 0u;  // wave propagates
-    }
-    bar<T>();
-    // scan of the wave summaries: carry into this wave, and out of the number
     uint32_t cin_w = cin, cout = cin;
+    if constexpr (W == 1) {
+        // one wave: its own summary is the whole scan
+        cout = (s0 < X ? 1u : 0u) | ((~P == 0 ? 1u : 0u) & cin);
+    } else {
+        if (lane() == 0) {
+            ctl[kCtlScan + 2 * w] = s0 < X ? 1u : 0u;      // wave generates
+            ctl[kCtlScan + 2 * w + 1] = (~P == 0) ? 1u : 0u;  // wave propagates
+        }
+        bar<T>();
+        // scan of the wave summaries: carry into this wave, and out of the number
 #pragma unroll
-    for (int v = 0; v < W; v++) {
-        if (v == w) cin_w = cout;
-        cout = ctl[kCtlScan + 2 * v] | (ctl[kCtlScan + 2 * v + 1] & cout);
+        for (int v = 0; v < W; v++) {
+            if (v == w) cin_w = cout;
+            cout = ctl[kCtlScan + 2 * v] | (ctl[kCtlScan + 2 * v + 1] & cout);
+        }
     }
     const uint64_t cm = (X + G + (uint64_t)cin_w) ^ X ^ G;
     uint32_t ci = (uint32_t)(cm >> lane()) & 1u;

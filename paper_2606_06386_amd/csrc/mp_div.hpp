@@ -435,19 +435,24 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     uint32_t red[3] = {0u, 0u, 0u};
     bar<T>();
     {
-        // four limbs of u and of v per thread and step, all read before use
-        const int nm = nu > nv ? nu : nv;
-        for (int i0 = tid(); i0 < nm; i0 += 4 * T) {
-            uint32_t ua[4], va[4];
+        // eight limbs of u and of v per thread and step, all read before use;
+        // v's limbs below nu also go to LDS right after the control block, where
+        // the divisor lives in every path that uses it (the allocation always
+        // holds kCtlWords + nu words)
+        uint32_t *V0 = lds + kCtlWords;
+        const int nm = nu > nv ? nu : nv, nvs = nu < nv ? nu : nv;
+        for (int i0 = tid(); i0 < nm; i0 += 8 * T) {
+            uint32_t ua[8], va[8];
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
+            for (int j = 0; j < 8; j++) {
                 const int i = i0 + j * T;
                 ua[j] = i < nu ? u[i] : 0u;
                 va[j] = i < nv ? v[i] : 0u;
             }
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
+            for (int j = 0; j < 8; j++) {
                 const int i = i0 + j * T;
+                if (i < nvs) V0[i] = va[j];
                 if (ua[j]) red[0] = (uint32_t)(i + 1);
                 if (va[j]) {
                     red[1] = (uint32_t)(i + 1);
@@ -472,7 +477,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         if (status && tid() == 0) *status = kInstOk;
         return;
     }
-    const uint32_t vk = v[k];
+    const uint32_t vk = lds[kCtlWords + k];      // k < nvv <= h <= nu: stored by the first pass
     const bool lowz = vlow == k;                  // v = v_k B^k
     if (k == 0) {                                 // single-limb divisor: short division of u
         uint32_t *scratch = lds + kCtlWords, *Q = scratch + 2 * T;
@@ -488,8 +493,8 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         const Plan pl = plan_div(h, k);
         uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
         uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP, *XR = lds + pl.offR;
-        // V = v; W, X, R and the window staging area (with its guards) = 0
-        copy<T>(V, k + 1, pl.offP - pl.offV, Vg);
+        // V = v (already there); W, X, R and the window staging area (with its guards) = 0
+        copy<T>(V + k + 1, 0, pl.offP - pl.offV - k - 1, Zero{});
         int we = 0, nw = 0, shf = 0, sbext = 0;
         bool good = true;
         if (k == h - 1 && (vk > 0x80000000u || (vk == 0x80000000u && !lowz))) {
