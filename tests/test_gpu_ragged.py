@@ -188,3 +188,32 @@ def test_ragged_graph_replay(mp):
         torch.cuda.synchronize()
         assert x.item() == (1 << 20) * ((1 << 20) - 1) // 2
         assert torch.equal(rb.q, q0) and torch.equal(rb.r, r0) and torch.equal(rb.status, s0), rep
+
+
+def test_tuner_configs_give_identical_results(mp, tmp_path):
+    """The autotuner picks a valid configuration per class and caches it; the
+    results of a mixed batch do not depend on the launch configuration."""
+    import torch
+    from paper_2606_06386_amd import tune
+    c = I.config_c4(index=np.arange(200, 248))
+    packed = R.pack(c["u"], c["v"])
+    outs = []
+    for cfg in ([(256, 1), (256, 1), (512, 1), (1024, 1)], [(1024, 8), (512, 2), (1024, 3), (1024, 2)]):
+        for cls, (t, g) in enumerate(cfg):
+            mp.ragged_config(cls, t, g)
+        rb = mp.Ragged(packed)
+        rb.run()
+        torch.cuda.synchronize()
+        outs.append((rb.q.cpu().numpy().copy(), rb.r.cpu().numpy().copy(), rb.status.cpu().numpy().copy()))
+    assert all((a == b).all() for a, b in zip(outs[0], outs[1]))
+    with pytest.raises(mp.MPError):
+        mp.ragged_config(3, 512, 1)                 # 8192 limbs need 1024 threads
+    best = tune.tune(counts=(32, 16, 8, 4), reps=1)
+    assert set(best) == {0, 1, 2, 3}
+    for cls, (t, g, ms) in best.items():
+        assert (t, g) in tune.candidates(cls) and ms > 0
+    cache = tmp_path / "tuned.json"
+    entry, fresh = tune.ensure(cache=str(cache))
+    assert fresh and cache.exists()
+    entry2, fresh2 = tune.ensure(cache=str(cache))
+    assert not fresh2 and entry2 == entry
