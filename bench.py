@@ -94,8 +94,6 @@ def measured_traffic(workload_name):
     path = os.path.join(ROOT, "profiles", f"k_divrem_{workload_name.split('_', 1)[1]}_traffic.json")
     if not os.path.exists(path):
         return None
-    if not os.path.exists(path):
-        return None
     rec = json.load(open(path))
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s_), "rb").read() for s_ in rec["sources"])).hexdigest()
     return rec["traffic_bytes_per_dispatch"] if h == rec["source_sha256"] else None

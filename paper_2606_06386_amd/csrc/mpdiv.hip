@@ -343,7 +343,11 @@ mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint
         hipStream_t fs = fork[dev][c];
         if (hipStreamWaitEvent(fs, ev_fork[dev], 0) != hipSuccess) return MP_ERR_LAUNCH;
         const int T = g_ragged.threads[c];
-        const size_t bytes = (size_t)mp::div_lds_words(kClassWidth[c], kClassWidth[c], T) * 4;
+        // LDS of the class's widest instance (a scan over every divisor length: computed once)
+        static size_t lds_bytes[kClasses][3];
+        const int ti = T == 256 ? 0 : T == 512 ? 1 : 2;
+        if (lds_bytes[c][ti] == 0) lds_bytes[c][ti] = (size_t)mp::div_lds_words(kClassWidth[c], kClassWidth[c], T) * 4;
+        const size_t bytes = lds_bytes[c][ti];
         if (bytes > (size_t)kLdsWords * 4) return MP_ERR_SIZE;
         const int fit = (int)(((size_t)kLdsWords * 4) / bytes);
         const int wpc = g_ragged.wgs_per_cu[c] < fit ? g_ragged.wgs_per_cu[c] : fit;
