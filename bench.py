@@ -100,7 +100,8 @@ def measured_traffic(workload_name):
 
 
 TRAFFIC_SOURCES = ["paper_2606_06386_amd/csrc/mp_prims_hip.hpp", "paper_2606_06386_amd/csrc/mp_core.hpp",
-                   "paper_2606_06386_amd/csrc/mp_div.hpp", "paper_2606_06386_amd/csrc/mpdiv.hip"]
+                   "paper_2606_06386_amd/csrc/mp_div.hpp", "paper_2606_06386_amd/csrc/launch.hpp",
+                   "paper_2606_06386_amd/csrc/kernels.hip", "paper_2606_06386_amd/csrc/mpdiv.hip"]
 
 
 def write_traffic(fetch_csv, write_csv, workload_name, kernel="k_divrem<"):
@@ -216,6 +217,78 @@ def roofline(W, ms, kernel, traffic, algo_bytes):
             "traffic": traffic, "traffic_unit": "bytes/launch", "algorithmic_bytes": algo_bytes,
             "kernel": kernel, "limb_products_per_s": W / (ms * 1e-3),
             "valu_mad_peak_limb_products_per_s": PEAK_LIMB_PRODUCTS}
+
+
+PHASES = [("load_prec", 0, 1), ("setup", 1, 2), ("initial_approx", 2, 3), ("one_wave_iters", 3, 4)]
+
+
+def phase_trace(args):
+    """Per-phase cycle breakdown of one k_divrem launch over the workload,
+    from the phase stamps of libmpdiv_trace.so (build.py --trace): shader
+    clock of workgroup thread 0 at each phase boundary, averaged over the
+    instances that pass every phase.  Prints one JSON line."""
+    import ctypes
+    import torch
+    from paper_2606_06386_amd import build as hb
+    hb.LIB = hb.TRACE_LIB                    # before the binding loads the library
+    from paper_2606_06386_amd import binding
+    set_knobs(args)
+    c = workload(args.config)
+    u_h, v_h, nq = c["u"], c["v"], c["nq"]
+    batch = len(u_h)
+    assert batch <= 8192 and threads_for(u_h.shape[1]) == 256, "the trace buffer covers k_divrem<256>, 8192 blocks"
+    dev = torch.device("cuda:0")
+    u = torch.from_numpy(u_h.view(np.int32)).to(dev)
+    v = torch.from_numpy(v_h.view(np.int32)).to(dev)
+    out = (torch.empty((batch, nq), dtype=torch.int32, device=dev),
+           torch.empty((batch, v_h.shape[1]), dtype=torch.int32, device=dev),
+           torch.empty(batch, dtype=torch.int32, device=dev))
+    for _ in range(max(1, args.warmup)):
+        binding.divrem(u, v, out=out)
+    torch.cuda.synchronize()
+    L = binding.lib()
+    L.mp_trace_read_divrem.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.mp_trace_read_divrem.restype = ctypes.c_int
+    st = np.zeros((batch, 32), dtype=np.uint64)
+    assert L.mp_trace_read_divrem(st.ctypes.data, batch) == 0
+    st = st.astype(np.float64)
+    full = (st[:, :9] > 0).all(axis=1) & (np.diff(st[:, :9], axis=1) >= 0).all(axis=1)
+    rows = st[full]
+    res = {}
+    for name, a, b in PHASES:
+        res[name] = float(np.mean(rows[:, b] - rows[:, a]))
+    prev = rows[:, 4].copy()
+    last = prev.copy()
+    for i in range(16):
+        col = rows[:, 16 + i]
+        if not (col > 0).any():
+            continue
+        res["iter_%d" % i] = float(np.mean(col - prev))
+        prev = np.where(col > 0, col, prev)
+        last = prev
+    res["u_times_s"] = float(np.mean(rows[:, 5] - last))
+    res["v_times_q"] = float(np.mean(rows[:, 6] - rows[:, 5]))
+    res["corrections"] = float(np.mean(rows[:, 7] - rows[:, 6]))
+    res["store"] = float(np.mean(rows[:, 8] - rows[:, 7]))
+    total = float(np.mean(rows[:, 8] - rows[:, 0]))
+    print(json.dumps({"phase_trace": c["name"], "kernel": "k_divrem<256>", "instances": int(full.sum()),
+                      "knobs": knobs_now(), "clock": "shader cycles (s_memtime) of workgroup thread 0",
+                      "total_cycles": total, "cycles": res,
+                      "share": {k: v / total for k, v in res.items()}}), flush=True)
+
+
+def set_knobs(args):
+    from paper_2606_06386_amd import binding
+    if args.mfma_min is not None:
+        binding.set_knob(binding.MP_KNOB_MFMA_MIN, args.mfma_min)
+    if args.small_limit is not None:
+        binding.set_knob(binding.MP_KNOB_SMALL_LIMIT, args.small_limit)
+
+
+def knobs_now():
+    from paper_2606_06386_amd import binding
+    return {"mfma_min": binding.get_knob(binding.MP_KNOB_MFMA_MIN),
+            "small_limit": binding.get_knob(binding.MP_KNOB_SMALL_LIMIT)}
 
 
 def run_mixed(args):
@@ -371,6 +444,12 @@ def main():
                     help="write the traffic record of --config's workload from two counter files and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--mfma-min", type=int, default=None,
+                    help="knob: shortest product operand (limbs) run on the matrix cores (huge = vector ALU only)")
+    ap.add_argument("--small-limit", type=int, default=None,
+                    help="knob: Refine iterations with a shorter iterate run on one wave")
+    ap.add_argument("--phase-trace", action="store_true",
+                    help="per-phase cycle breakdown from the trace build of the library instead")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(*args.write_traffic, workload_name={"c1": "divrem_2p15_b1024", "c2": "divrem_2p16_b4096",
@@ -388,6 +467,10 @@ def main():
     if args.probe:
         probe_rates()
         return
+    if args.phase_trace:
+        phase_trace(args)
+        return
+    set_knobs(args)
     if args.config == "c4":
         run_mixed(args)
         return
@@ -447,6 +530,7 @@ def main():
         "roofline": roofline(W, kmean, "k_divrem<%d>" % threads_for(u_h.shape[1]), measured_traffic(c["name"]),
                              algo_bytes),
         "status_ok": int((status == 0).sum()),
+        "knobs": knobs_now(),
     }
     if args.copy_calibration:
         x = torch.empty(64 << 20, dtype=torch.int32, device=dev)

@@ -129,6 +129,34 @@ int64_t mp_ragged_workspace_bytes(int32_t count);
  */
 mp_status_t mp_ragged_config(int32_t cls, int32_t threads, int32_t wgs_per_cu);
 
+/*
+ * Run-time tuning knobs of the division kernels (process-wide; a change
+ * applies to launches made after it).  Every setting gives the same results
+ * bit for bit; only the speed differs.
+ *   MP_KNOB_MFMA_MIN     products whose shorter operand has at least this many
+ *                        limbs (>= 1) run on the int8 matrix cores as exact
+ *                        balanced radix-256 digit products; shorter ones on the
+ *                        vector ALU (32x32->64-bit multiply-adds).  Default 64.
+ *   MP_KNOB_SMALL_LIMIT  Refine iterations of Alg. 1 whose iterate has fewer
+ *                        than this many limbs (0..256) run on a single wave of
+ *                        the workgroup.  Default 64.
+ * mp_set_knob returns MP_ERR_ARG for an unknown knob or a value out of range;
+ * mp_get_knob returns the current value (-1 for an unknown knob).
+ */
+enum { MP_KNOB_MFMA_MIN = 0, MP_KNOB_SMALL_LIMIT = 1 };
+mp_status_t mp_set_knob(int32_t knob, int32_t value);
+int32_t mp_get_knob(int32_t knob);
+
+/*
+ * Dynamic LDS bytes per workgroup that a launch needs (host-side query, no
+ * device call): MP_OP_MUL with (na, nb), MP_OP_DIVREM with (nu, nv),
+ * MP_OP_SHINV with (nv, h).  Returns -1 for an unknown op or a width outside
+ * [1, mp_max_limbs()].  A launch whose figure exceeds the 160 KB of one
+ * gfx950 workgroup returns MP_ERR_SIZE.
+ */
+enum { MP_OP_MUL = 0, MP_OP_DIVREM = 1, MP_OP_SHINV = 2 };
+int64_t mp_lds_bytes(int32_t op, int32_t n1, int32_t n2);
+
 /* human-readable name of a status code (static storage) */
 const char *mp_status_str(mp_status_t s);
 

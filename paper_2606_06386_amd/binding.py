@@ -18,7 +18,9 @@ MP_INST_OK, MP_INST_DIVZERO, MP_INST_QWIDTH, MP_INST_INTERNAL, MP_INST_BADDESC =
 
 # every entry point declared in include/mpdiv.h
 EXPORTS = ("mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_divrem_ragged", "mp_ragged_workspace_bytes",
-           "mp_ragged_config", "mp_status_str", "mp_max_limbs")
+           "mp_ragged_config", "mp_set_knob", "mp_get_knob", "mp_lds_bytes", "mp_status_str", "mp_max_limbs")
+MP_KNOB_MFMA_MIN, MP_KNOB_SMALL_LIMIT = 0, 1
+MP_OP_MUL, MP_OP_DIVREM, MP_OP_SHINV = 0, 1, 2
 
 _lib = None
 _vp, _i32 = ctypes.c_void_p, ctypes.c_int32
@@ -48,6 +50,12 @@ def lib():
         L.mp_ragged_workspace_bytes.restype = _i64
         L.mp_ragged_config.argtypes = [_i32, _i32, _i32]
         L.mp_ragged_config.restype = _i32
+        L.mp_set_knob.argtypes = [_i32, _i32]
+        L.mp_set_knob.restype = _i32
+        L.mp_get_knob.argtypes = [_i32]
+        L.mp_get_knob.restype = _i32
+        L.mp_lds_bytes.argtypes = [_i32, _i32, _i32]
+        L.mp_lds_bytes.restype = _i64
         L.mp_max_limbs.argtypes = []
         L.mp_status_str.argtypes = [_i32]
         L.mp_status_str.restype = ctypes.c_char_p
@@ -145,6 +153,20 @@ class Ragged:
                                       self.desc.data_ptr(), self.q.data_ptr(), self.q.numel(), self.r.data_ptr(),
                                       self.r.numel(), self.status.data_ptr(), self.count, self.ws.data_ptr(),
                                       _stream(stream)), "mp_divrem_ragged")
+
+
+def set_knob(knob, value):
+    """Set a run-time tuning knob (see mp_set_knob)."""
+    _raise(lib().mp_set_knob(knob, value), "mp_set_knob")
+
+
+def get_knob(knob):
+    return int(lib().mp_get_knob(knob))
+
+
+def lds_bytes(op, n1, n2):
+    """Dynamic LDS bytes per workgroup of a launch (see mp_lds_bytes)."""
+    return int(lib().mp_lds_bytes(op, n1, n2))
 
 
 def ragged_config(cls, threads, wgs_per_cu):

@@ -564,7 +564,6 @@ struct StoreBalRev {
 
 constexpr int kYPad = 248;   // zero limbs the long operand's digits need on each side (31 blocks)
 constexpr int kXPad = 16;    // zero words the reversed short operand needs on each side
-constexpr int kMfmaMin = 64; // shortest operand (limbs) for which the matrix-core product pays
 
 // Balanced digits of the long operand (ny limbs) into yb[0 .. ny] and of the
 // short operand (nx limbs) byte-reversed into xr[0 .. nx]; yb keeps kYPad zero

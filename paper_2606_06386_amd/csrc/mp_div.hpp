@@ -24,6 +24,8 @@
 
 #include <stdint.h>
 
+#include "launch.hpp"
+
 namespace mp {
 
 enum : int32_t { kInstOk = 0, kInstDivZero = 1, kInstQWidth = 2, kInstInternal = 3 };
@@ -95,9 +97,9 @@ MP_HD int mul_lds_words(int na, int nb)
 template <int T, class FL, class FS>
 MP_DEV int product_views(uint32_t *ctl, uint32_t *p, int ncols, const FL &lng, int nl, const uint32_t *lng_lds,
                          const FS &sht, int ns, const uint32_t *sht_lds, uint32_t *sb, int &sbext,
-                         uint32_t *xr, int xrcap, int c0 = 0, bool want_prec = true)
+                         uint32_t *xr, int xrcap, int mfma_min, int c0 = 0, bool want_prec = true)
 {
-    if (ns >= kMfmaMin && ns + 1 <= xrcap) {
+    if (ns >= mfma_min && ns + 1 <= xrcap) {
         mfma_operands<T>(ctl, lng, nl, sb, sbext, sht, ns, xr);
         sbext = nl + 1;
         return mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0, want_prec);
@@ -109,13 +111,13 @@ MP_DEV int product_views(uint32_t *ctl, uint32_t *p, int ncols, const FL &lng, i
 
 template <int T>
 MP_DEV int product(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *x, int nx,
-                   const uint32_t *y, int ny, uint32_t *sb, int &sbext, uint32_t *xr, int xrcap, int c0 = 0,
-                   bool want_prec = true)
+                   const uint32_t *y, int ny, uint32_t *sb, int &sbext, uint32_t *xr, int xrcap, int mfma_min,
+                   int c0 = 0, bool want_prec = true)
 {
     const uint32_t *sht = nx >= ny ? y : x, *lng = nx >= ny ? x : y;
     const int ns = nx >= ny ? ny : nx, nl = nx >= ny ? nx : ny;
     return product_views<T>(ctl, p, ncols, Span{lng, 0, nl}, nl, lng, Span{sht, 0, ns}, ns, sht, sb, sbext,
-                            xr, xrcap, c0, want_prec);
+                            xr, xrcap, mfma_min, c0, want_prec);
 }
 
 // dst[0, n) = src limbs [0, e) zero-padded, where e = prec(src) must be <= n;
@@ -157,8 +159,8 @@ MP_DEV int ceil_log2(int x)   // x >= 1
 // iterate W (nonzero limbs inside [0, we), precision nw) and l.  Run by T
 // threads (the workgroup, or one wave for the small early iterations).
 template <int T>
-MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, int i, int &l, int &we,
-                        int &nw, int &sbext)
+MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t *lds, int h, int k, int i, int &l,
+                        int &we, int &nw, int &sbext)
 {
     uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
     uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP, *XR = lds + pl.offR;
@@ -175,7 +177,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int
     if (L >= hp) {                      // full product, compare with B^hp
         const int np0 = nvp + nw;
         if (np0 > pl.capP) return false;
-        const int np = product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR);
+        const int np = product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR, kn.mfma_min);
         if (np <= hp) {                 // P < B^hp: x = B^hp - P
             if (hp > pl.capX) return false;
             sign = true;
@@ -188,7 +190,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int
         nx = read_prec<T>(ctl);
     } else {                            // close product: P = v'w mod B^L
         if (L > pl.capP || L > pl.capX) return false;
-        const int np = product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR);
+        const int np = product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR, kn.mfma_min);
         if (np == 0) {                  // v'w = B^hp exactly
             sign = true;
             nx = 0;
@@ -219,7 +221,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int
         cs = nt >= sh + 2 ? imax(sh - 2, 0) & ~7 : 0;
         if (cs) nt += 1;
         if (nt > pl.capP) return false;
-        product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, cs, false);
+        product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, kn.mfma_min, cs, false);
     }
     uint32_t sticky = 0;
     if (!sign && nt > cs) {
@@ -242,11 +244,11 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int
 // On return the shifted inverse is the limbs of W above `shf`; W's nonzero
 // limbs lie inside [0, we) and nw = prec(W).  Returns false if a capacity
 // guard trips or a Step result turns negative (never expected).  The early
-// iterations, whose operands are all shorter than kMfmaMin limbs, run on the
+// iterations, whose iterate is shorter than kn.small_limit limbs, run on the
 // first wave alone (no workgroup barriers) while the others wait.
 template <int T>
-MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, int &we, int &nw, int &shf,
-                   int &sbext)
+MP_DEV bool refine(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t *lds, int h, int k, int &we, int &nw,
+                   int &shf, int &sbext)
 {
     uint32_t *V = lds + pl.offV, *W = lds + pl.offW;
     const int g = 2, d = h - k;
@@ -263,20 +265,21 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
         ctl[kCtlBcast + 1] = W[4] ? 5u : W[3] ? 4u : 3u;
     }
     bar<T>();
+    MP_STAMP(3);
     nw = (int)uniform(ctl[kCtlBcast + 1]);
     we = 5;
     int l = 2;
     const int iters = 2 + (d - 1 <= 1 ? 0 : ceil_log2(d - 1));
     int i = 0;
     if constexpr (T > kLanes) {
-        int nsmall = 0;                       // iterations with an iterate of l + g + 1 < kMfmaMin limbs
-        for (int ll = 2; nsmall < iters && ll + g + 1 < kMfmaMin; nsmall++)
+        int nsmall = 0;                       // iterations with an iterate of l + g + 1 < small_limit limbs
+        for (int ll = 2; nsmall < iters && ll + g + 1 < kn.small_limit; nsmall++)
             if (nsmall >= 2) ll = ll + imin(d + 1 - ll, ll) - 1;
         if (nsmall > 0) {
             if (tid() < kLanes) {
                 bool ok = true;
                 int l1 = l, we1 = we, nw1 = nw, sb1 = sbext;
-                for (int j = 0; j < nsmall && ok; j++) ok = refine_iter<kLanes>(ctl, pl, lds, h, k, j, l1, we1, nw1, sb1);
+                for (int j = 0; j < nsmall && ok; j++) ok = refine_iter<kLanes>(ctl, pl, kn, lds, h, k, j, l1, we1, nw1, sb1);
                 if (tid() == 0) {
                     ctl[kCtlBcast + 3] = ok ? 1u : 0u;
                     ctl[kCtlBcast + 4] = (uint32_t)l1;
@@ -286,6 +289,7 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
                 }
             }
             sync();
+            MP_STAMP(4);
             if (!uniform(ctl[kCtlBcast + 3])) return false;
             l = (int)uniform(ctl[kCtlBcast + 4]);
             we = (int)uniform(ctl[kCtlBcast + 5]);
@@ -294,8 +298,10 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
             i = nsmall;
         }
     }
-    for (; i < iters; i++)
-        if (!refine_iter<T>(ctl, pl, lds, h, k, i, l, we, nw, sbext)) return false;
+    for (; i < iters; i++) {
+        if (!refine_iter<T>(ctl, pl, kn, lds, h, k, i, l, we, nw, sbext)) return false;
+        MP_STAMP(16 + (i & 15));
+    }
     shf = d < 2 ? 4 - d : 2;
     return true;
 }
@@ -304,7 +310,8 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, uint32_t *lds, int h, int k, i
 
 // c = a * b  (c has na + nb limbs)
 template <int T>
-MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_t *b, int nb, uint32_t *c)
+MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_t *b, int nb, uint32_t *c,
+                         const Knobs &kn)
 {
     uint32_t *ctl = lds;
     const int nlo = na < nb ? na : nb, nhi = na < nb ? nb : na;
@@ -314,7 +321,7 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
     uint32_t *SB = SBbase + kPad;                   // long operand (window, or digits)
     uint32_t *P = SB + r4(nhi + 1) + kPad;
     int np;
-    if (nlo >= kMfmaMin) {
+    if (nlo >= kn.mfma_min) {
         copy<T>(SBbase, 0, 2 * kPad + r4(nhi + 1), Zero{});
         mfma_operands<T>(ctl, Span{lng, 0, nhi}, nhi, SB, 0, Span{sht, 0, nlo}, nlo, A);
         np = mul_mfma<T>(ctl, P, na + nb, SB, nhi, A, nlo, 0, false);
@@ -331,7 +338,7 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
 // w = floor(B^h / v), exactly (nw limbs)
 template <int T>
 MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint32_t *w, int nw,
-                           int32_t *status)
+                           int32_t *status, const Knobs &kn)
 {
     uint32_t *ctl = lds;
     const Span Vg{v, 0, nv};
@@ -371,7 +378,7 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
         copy<T>(W, 0, pl.capW, Zero{});
         copy<T>(SB - kPad, 0, pl.capSB + 2 * kPad, Zero{});
         int we = 0, nwi = 0, shf = 0, sbext = 0;
-        if (!refine<T>(ctl, pl, lds, h, k, we, nwi, shf, sbext)) {
+        if (!refine<T>(ctl, pl, kn, lds, h, k, we, nwi, shf, sbext)) {
             st = kInstInternal;
         } else {
             // exact fix-up: D = B^h - v s with s within two of floor(B^h/v), so
@@ -385,7 +392,7 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
             const int full = k + 1 + ns;
             const int Lr = d >= 3 ? k + 3 : imax(full, h + 1) + 1;
             const int pc = imin(Lr, full);
-            product<T>(ctl, P, pc, V, k + 1, S, ns, SB, sbext, XR, pl.capR, 0, false);
+            product<T>(ctl, P, pc, V, k + 1, S, ns, SB, sbext, XR, pl.capR, kn.mfma_min, 0, false);
             addsub<T>(ctl, Lr, true, 0u, PowB{h}, Span{P, 0, pc}, Store{X, 0, Lr});
             uint32_t *R = X, *R2 = P;
             int adj = 0;
@@ -425,7 +432,7 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
 // (q, r) with u = q v + r, 0 <= r < v  (q: nq limbs, r: nv limbs)
 template <int T>
 MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint32_t *v, int nv,
-                            uint32_t *q, int nq, uint32_t *r, int32_t *status)
+                            uint32_t *q, int nq, uint32_t *r, int32_t *status, const Knobs &kn)
 {
     uint32_t *ctl = lds;
     const Span Ug{u, 0, nu}, Vg{v, 0, nv};
@@ -434,6 +441,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     // one pass over u and v: prec(u), prec(v), and the lowest nonzero limb of v
     uint32_t red[3] = {0u, 0u, 0u};
     bar<T>();
+    MP_STAMP(0);
     {
         // eight limbs of u and of v per thread and step, all read before use;
         // v's limbs below nu also go to LDS right after the control block, where
@@ -462,6 +470,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         }
     }
     wg_max_n<T, 3>(ctl, red);
+    MP_STAMP(1);
     const int h = (int)red[0], nvv = (int)red[1], vlow = nv - (int)red[2];
     if (nvv == 0) {
         store_zero<T>(q, nq);
@@ -495,6 +504,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         uint32_t *SB = lds + pl.offSB, *P = lds + pl.offP, *XR = lds + pl.offR;
         // V = v (already there); W, X, R and the window staging area (with its guards) = 0
         copy<T>(V + k + 1, 0, pl.offP - pl.offV - k - 1, Zero{});
+        MP_STAMP(2);
         int we = 0, nw = 0, shf = 0, sbext = 0;
         bool good = true;
         if (k == h - 1 && (vk > 0x80000000u || (vk == 0x80000000u && !lowz))) {
@@ -504,7 +514,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
             nw = 1;
             shf = 0;
         } else {
-            good = refine<T>(ctl, pl, lds, h, k, we, nw, shf, sbext);
+            good = refine<T>(ctl, pl, kn, lds, h, k, we, nw, shf, sbext);
         }
         if (good) {
             // q0 = shift_{-h}(u * s)
@@ -518,7 +528,8 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
                 // cores, whose digit products below c0 may be negative)
                 const int c0 = imax(h - 2, 0) & ~7;
                 const int np = product_views<T>(ctl, P, h + ns, Ug, h, nullptr, Span{S, 0, ns}, ns, S, SB, sbext,
-                                                XR, pl.capR, c0);
+                                                XR, pl.capR, kn.mfma_min, c0);
+                MP_STAMP(5);
                 const int nq0 = imax(np - h, 0);
                 copy<T>(W, nq0, we, Span{P, -h, h + ns});
                 we = nq0;
@@ -528,7 +539,8 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
                 // (k+2)-limb number and only the low k+2 limbs of m = v q0 are
                 // needed.  The loops below allow one more step each way.
                 const int rl = k + 2;
-                product<T>(ctl, P, rl, W, nq0, V, k + 1, SB, sbext, XR, pl.capR, 0, false);
+                product<T>(ctl, P, rl, W, nq0, V, k + 1, SB, sbext, XR, pl.capR, kn.mfma_min, 0, false);
+                MP_STAMP(6);
                 uint32_t *R = SB, *R2 = X;
                 int delta = 0;
                 addsub<T>(ctl, rl, true, 0u, Ug, Span{P, 0, rl}, Store{R, 0, rl});
@@ -555,6 +567,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
                               Store{W, 0, we + 1});
                     we += 1;
                 }
+                MP_STAMP(7);
                 if (good) {
                     ok = store_fit<T>(ctl, q, nq, we, Span{W, 0, we});
                     if (ok)
@@ -571,6 +584,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         store_zero<T>(r, nv);
     }
     if (status && tid() == 0) *status = st;
+    MP_STAMP(8);
 }
 
 }  // namespace mp

@@ -11,6 +11,22 @@
 
 #define MP_DEV __device__ __forceinline__
 
+// Phase tracing (a diagnostic build option, off by default): with
+// MP_PHASE_TRACE defined, MP_STAMP(id) records the shader clock of
+// workgroup thread 0 in slot id (< 32) of the workgroup's row of
+// mp_trace_buf (one per translation unit, for up to 8192 workgroups).
+#ifdef MP_PHASE_TRACE
+static __device__ uint64_t mp_trace_buf[8192 * 32];
+#define MP_STAMP(id)                                                                                 \
+    do {                                                                                             \
+        if (threadIdx.x == 0) mp_trace_buf[(size_t)blockIdx.x * 32 + (id)] = __builtin_readcyclecounter(); \
+    } while (0)
+#else
+#define MP_STAMP(id) \
+    do {             \
+    } while (0)
+#endif
+
 namespace mp {
 
 constexpr int kLanes = 64;  // CDNA wavefront width

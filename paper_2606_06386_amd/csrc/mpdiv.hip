@@ -1,55 +1,26 @@
-// Kernels and C ABI of libmpdiv (see include/mpdiv.h).
-//
-// One workgroup per instance.  The workgroup size follows the operand width
-// so that every linear pass handles at most 16 limbs per thread:
-//   width <= 2048 limbs -> 256 threads, <= 4096 -> 512, <= 8192 -> 1024.
-// All operands and intermediates of an instance live in dynamic LDS laid out
-// by plan_div (about 4h + 800 words: 36 KB at 2^16 bits, 134 KB at 2^18).
+// C ABI of libmpdiv (see include/mpdiv.h): argument checks, launch
+// configuration and the ragged-batch preparation kernel.  The division
+// kernels themselves are in kernels.hip.
 #include "mp_prims_hip.hpp"
 #include "mp_core.hpp"
 #include "mp_div.hpp"
+#include "launch.hpp"
 
 #include "../../include/mpdiv.h"
 
+#include <atomic>
 #include <mutex>
 #include <string.h>
 
 namespace {
 
 constexpr int kMaxLimbs = 8192;
-
-// Division kernels ask the compiler for at most 128 registers per lane, so
-// that four waves share each SIMD: four 256-thread workgroups per compute
-// unit at 2^16 bits, where the LDS plan also allows four.
-#define MP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4, 8)))
 constexpr int kLdsWords = 160 * 1024 / 4;   // gfx950: 160 KB of LDS per workgroup
 
-template <int T>
-__global__ __launch_bounds__(T) void k_mul(const uint32_t *a, int na, const uint32_t *b, int nb, uint32_t *c)
-{
-    extern __shared__ __align__(16) uint32_t lds[];
-    const size_t j = blockIdx.x;
-    mp::mul_instance<T>(lds, a + j * na, na, b + j * nb, nb, c + j * (size_t)(na + nb));
-}
+// run-time knobs (mp_set_knob)
+std::atomic<int32_t> g_mfma_min{64}, g_small_limit{64};
 
-template <int T>
-__global__ __launch_bounds__(T) MP_OCCUPANCY void k_shinv(const uint32_t *v, int nv, int h, uint32_t *w, int nw,
-                                             int32_t *status)
-{
-    extern __shared__ __align__(16) uint32_t lds[];
-    const size_t j = blockIdx.x;
-    mp::shinv_instance<T>(lds, v + j * nv, nv, h, w + j * nw, nw, status ? status + j : nullptr);
-}
-
-template <int T>
-__global__ __launch_bounds__(T) MP_OCCUPANCY void k_divrem(const uint32_t *u, int nu, const uint32_t *v, int nv,
-                                              uint32_t *q, int nq, uint32_t *r, int32_t *status)
-{
-    extern __shared__ __align__(16) uint32_t lds[];
-    const size_t j = blockIdx.x;
-    mp::divrem_instance<T>(lds, u + j * nu, nu, v + j * nv, nv, q + j * nq, nq, r + j * nv,
-                           status ? status + j : nullptr);
-}
+mp::Knobs knobs() { return mp::Knobs{g_mfma_min.load(), g_small_limit.load()}; }
 
 // ------------------------------------------------------------ ragged batches
 //
@@ -92,37 +63,6 @@ __global__ __launch_bounds__(1024) void k_ragged_prep(const mp_desc_t *desc, int
     }
 }
 
-__device__ __forceinline__ int64_t uniform64(int64_t x)
-{
-    const uint32_t lo = mp::uniform((uint32_t)x), hi = mp::uniform((uint32_t)((uint64_t)x >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// persistent workgroups of one class: take the next instance of the class's
-// queue until it is empty
-template <int T>
-__global__ __launch_bounds__(T) MP_OCCUPANCY void k_ragged(const uint32_t *up, const uint32_t *vp, const mp_desc_t *desc,
-                                              uint32_t *qp, uint32_t *rp, int32_t *status, int32_t *ws, int cls,
-                                              int count)
-{
-    extern __shared__ __align__(16) uint32_t lds[];
-    const int n = ws[cls];
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) lds[mp::kCtlBcast + 2] = (uint32_t)atomicAdd(&ws[kClasses + cls], 1);
-        __syncthreads();
-        // every value below is the same on all lanes: keep it in scalar registers
-        const int idx = mp::uniform((int)lds[mp::kCtlBcast + 2]);
-        if (idx >= n) break;
-        const int j = mp::uniform(ws[kWsHeader + (size_t)cls * count + idx]);
-        const mp_desc_t &d = desc[j];
-        const int64_t uo = uniform64(d.u_off), vo = uniform64(d.v_off), qo = uniform64(d.q_off),
-                      ro = uniform64(d.r_off);
-        const int nu = mp::uniform(d.nu), nv = mp::uniform(d.nv), nq = mp::uniform(d.nq);
-        mp::divrem_instance<T>(lds, up + uo, nu, vp + vo, nv, qp + qo, nq, rp + ro, status + j);
-    }
-}
-
 struct RaggedConfig {
     int threads[kClasses] = {256, 256, 512, 1024};
     int wgs_per_cu[kClasses] = {6, 3, 2, 1};
@@ -150,16 +90,12 @@ bool device_ok()
     return checked[dev] == 1;
 }
 
-mp_status_t finish_launch()
-{
-    return hipGetLastError() == hipSuccess ? MP_OK : MP_ERR_LAUNCH;
-}
+}  // namespace
 
 // raise a kernel's dynamic LDS limit to at least `bytes` on the current
 // device; the attribute is set only when it grows, so repeated launches (and
 // launches under stream capture) make no further runtime call
-template <typename Kern>
-bool set_lds(Kern kernel, size_t bytes)
+bool mp::lds_attr(const void *fn, size_t bytes)
 {
     struct Entry {
         const void *fn;
@@ -169,7 +105,6 @@ bool set_lds(Kern kernel, size_t bytes)
     static Entry seen[256];
     static int nseen;
     static std::mutex mu;
-    const void *fn = reinterpret_cast<const void *>(kernel);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     std::lock_guard<std::mutex> lock(mu);
@@ -182,6 +117,10 @@ bool set_lds(Kern kernel, size_t bytes)
     if (e) *e = Entry{fn, dev, bytes};
     return true;
 }
+
+namespace {
+
+mp_status_t status_of(hipError_t e) { return e == hipSuccess ? MP_OK : MP_ERR_LAUNCH; }
 
 }  // namespace
 
@@ -201,6 +140,47 @@ const char *mp_status_str(mp_status_t s)
 
 int32_t mp_max_limbs(void) { return kMaxLimbs; }
 
+mp_status_t mp_set_knob(int32_t knob, int32_t value)
+{
+    switch (knob) {
+    case MP_KNOB_MFMA_MIN:
+        if (value < 1) return MP_ERR_ARG;
+        g_mfma_min.store(value);
+        return MP_OK;
+    case MP_KNOB_SMALL_LIMIT:
+        if (value < 0 || value > 256) return MP_ERR_ARG;
+        g_small_limit.store(value);
+        return MP_OK;
+    }
+    return MP_ERR_ARG;
+}
+
+int32_t mp_get_knob(int32_t knob)
+{
+    switch (knob) {
+    case MP_KNOB_MFMA_MIN: return g_mfma_min.load();
+    case MP_KNOB_SMALL_LIMIT: return g_small_limit.load();
+    }
+    return -1;
+}
+
+int64_t mp_lds_bytes(int32_t op, int32_t n1, int32_t n2)
+{
+    if (n1 <= 0 || n2 <= 0 || n1 > kMaxLimbs || n2 > kMaxLimbs) return -1;
+    switch (op) {
+    case MP_OP_MUL: return (int64_t)4 * mp::mul_lds_words(n1, n2);
+    case MP_OP_DIVREM: return (int64_t)4 * mp::div_lds_words(n1, n2, threads_for(n1));
+    case MP_OP_SHINV: {
+        const int T = threads_for(n2);
+        int words = mp::plan_short_words(n2 + 1, T);
+        const int kmax = (n1 < n2 ? n1 : n2) - 1;
+        for (int k = 1; k <= kmax; k++) words = mp::hmax(words, mp::plan_div(n2, k).total);
+        return (int64_t)4 * words;
+    }
+    }
+    return -1;
+}
+
 mp_status_t mp_mul_batch(const uint32_t *a, int32_t na, const uint32_t *b, int32_t nb,
                          uint32_t *c, int32_t batch, void *stream)
 {
@@ -212,21 +192,12 @@ mp_status_t mp_mul_batch(const uint32_t *a, int32_t na, const uint32_t *b, int32
     if (words > kLdsWords) return MP_ERR_SIZE;
     const size_t bytes = (size_t)words * 4;
     hipStream_t st = (hipStream_t)stream;
+    const mp::Knobs kn = knobs();
     switch (threads_for((na + nb + 1) / 2)) {
-    case 256:
-        if (!set_lds(k_mul<256>, bytes)) return MP_ERR_LAUNCH;
-        hipLaunchKernelGGL(k_mul<256>, dim3(batch), dim3(256), bytes, st, a, na, b, nb, c);
-        break;
-    case 512:
-        if (!set_lds(k_mul<512>, bytes)) return MP_ERR_LAUNCH;
-        hipLaunchKernelGGL(k_mul<512>, dim3(batch), dim3(512), bytes, st, a, na, b, nb, c);
-        break;
-    default:
-        if (!set_lds(k_mul<1024>, bytes)) return MP_ERR_LAUNCH;
-        hipLaunchKernelGGL(k_mul<1024>, dim3(batch), dim3(1024), bytes, st, a, na, b, nb, c);
-        break;
+    case 256: return status_of(mp::launch_mul<256>(batch, bytes, st, a, na, b, nb, c, kn));
+    case 512: return status_of(mp::launch_mul<512>(batch, bytes, st, a, na, b, nb, c, kn));
+    default: return status_of(mp::launch_mul<1024>(batch, bytes, st, a, na, b, nb, c, kn));
     }
-    return finish_launch();
 }
 
 mp_status_t mp_shinv_batch(const uint32_t *v, int32_t nv, int32_t h, uint32_t *w, int32_t nw,
@@ -243,21 +214,12 @@ mp_status_t mp_shinv_batch(const uint32_t *v, int32_t nv, int32_t h, uint32_t *w
     if (words > kLdsWords) return MP_ERR_SIZE;
     const size_t bytes = (size_t)words * 4;
     hipStream_t st = (hipStream_t)stream;
+    const mp::Knobs kn = knobs();
     switch (T) {
-    case 256:
-        if (!set_lds(k_shinv<256>, bytes)) return MP_ERR_LAUNCH;
-        hipLaunchKernelGGL(k_shinv<256>, dim3(batch), dim3(256), bytes, st, v, nv, h, w, nw, inst_status);
-        break;
-    case 512:
-        if (!set_lds(k_shinv<512>, bytes)) return MP_ERR_LAUNCH;
-        hipLaunchKernelGGL(k_shinv<512>, dim3(batch), dim3(512), bytes, st, v, nv, h, w, nw, inst_status);
-        break;
-    default:
-        if (!set_lds(k_shinv<1024>, bytes)) return MP_ERR_LAUNCH;
-        hipLaunchKernelGGL(k_shinv<1024>, dim3(batch), dim3(1024), bytes, st, v, nv, h, w, nw, inst_status);
-        break;
+    case 256: return status_of(mp::launch_shinv<256>(batch, bytes, st, v, nv, h, w, nw, inst_status, kn));
+    case 512: return status_of(mp::launch_shinv<512>(batch, bytes, st, v, nv, h, w, nw, inst_status, kn));
+    default: return status_of(mp::launch_shinv<1024>(batch, bytes, st, v, nv, h, w, nw, inst_status, kn));
     }
-    return finish_launch();
 }
 
 mp_status_t mp_divrem_batch(const uint32_t *u, int32_t nu, const uint32_t *v, int32_t nv,
@@ -273,21 +235,12 @@ mp_status_t mp_divrem_batch(const uint32_t *u, int32_t nu, const uint32_t *v, in
     if (words > kLdsWords) return MP_ERR_SIZE;
     const size_t bytes = (size_t)words * 4;
     hipStream_t st = (hipStream_t)stream;
+    const mp::Knobs kn = knobs();
     switch (T) {
-    case 256:
-        if (!set_lds(k_divrem<256>, bytes)) return MP_ERR_LAUNCH;
-        hipLaunchKernelGGL(k_divrem<256>, dim3(batch), dim3(256), bytes, st, u, nu, v, nv, q, nq, r, inst_status);
-        break;
-    case 512:
-        if (!set_lds(k_divrem<512>, bytes)) return MP_ERR_LAUNCH;
-        hipLaunchKernelGGL(k_divrem<512>, dim3(batch), dim3(512), bytes, st, u, nu, v, nv, q, nq, r, inst_status);
-        break;
-    default:
-        if (!set_lds(k_divrem<1024>, bytes)) return MP_ERR_LAUNCH;
-        hipLaunchKernelGGL(k_divrem<1024>, dim3(batch), dim3(1024), bytes, st, u, nu, v, nv, q, nq, r, inst_status);
-        break;
+    case 256: return status_of(mp::launch_divrem<256>(batch, bytes, st, u, nu, v, nv, q, nq, r, inst_status, kn));
+    case 512: return status_of(mp::launch_divrem<512>(batch, bytes, st, u, nu, v, nv, q, nq, r, inst_status, kn));
+    default: return status_of(mp::launch_divrem<1024>(batch, bytes, st, u, nu, v, nv, q, nq, r, inst_status, kn));
     }
-    return finish_launch();
 }
 
 int64_t mp_ragged_workspace_bytes(int32_t count)
@@ -339,6 +292,7 @@ mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint
     hipLaunchKernelGGL(k_ragged_prep, dim3(1), dim3(1024), 0, st, desc, count, u_limbs, v_limbs, q_limbs,
                        r_limbs, inst_status, ws);
     if (hipGetLastError() != hipSuccess || hipEventRecord(ev_fork[dev], st) != hipSuccess) return MP_ERR_LAUNCH;
+    const mp::Knobs kn = knobs();
     for (int c = 0; c < kClasses; c++) {
         hipStream_t fs = fork[dev][c];
         if (hipStreamWaitEvent(fs, ev_fork[dev], 0) != hipSuccess) return MP_ERR_LAUNCH;
@@ -351,25 +305,14 @@ mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint
         if (bytes > (size_t)kLdsWords * 4) return MP_ERR_SIZE;
         const int fit = (int)(((size_t)kLdsWords * 4) / bytes);
         const int wpc = g_ragged.wgs_per_cu[c] < fit ? g_ragged.wgs_per_cu[c] : fit;
-        const dim3 grid(cus[dev] * wpc);
+        const int grid = cus[dev] * wpc;
+        hipError_t e;
         switch (T) {
-        case 256:
-            if (!set_lds(k_ragged<256>, bytes)) return MP_ERR_LAUNCH;
-            hipLaunchKernelGGL(k_ragged<256>, grid, dim3(256), bytes, fs, u_pool, v_pool, desc, q_pool, r_pool,
-                               inst_status, ws, c, count);
-            break;
-        case 512:
-            if (!set_lds(k_ragged<512>, bytes)) return MP_ERR_LAUNCH;
-            hipLaunchKernelGGL(k_ragged<512>, grid, dim3(512), bytes, fs, u_pool, v_pool, desc, q_pool, r_pool,
-                               inst_status, ws, c, count);
-            break;
-        default:
-            if (!set_lds(k_ragged<1024>, bytes)) return MP_ERR_LAUNCH;
-            hipLaunchKernelGGL(k_ragged<1024>, grid, dim3(1024), bytes, fs, u_pool, v_pool, desc, q_pool, r_pool,
-                               inst_status, ws, c, count);
-            break;
+        case 256: e = mp::launch_ragged<256>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c, count, kn); break;
+        case 512: e = mp::launch_ragged<512>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c, count, kn); break;
+        default: e = mp::launch_ragged<1024>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c, count, kn); break;
         }
-        if (hipGetLastError() != hipSuccess || hipEventRecord(ev_join[dev][c], fs) != hipSuccess ||
+        if (e != hipSuccess || hipEventRecord(ev_join[dev][c], fs) != hipSuccess ||
             hipStreamWaitEvent(st, ev_join[dev][c], 0) != hipSuccess)
             return MP_ERR_LAUNCH;
     }

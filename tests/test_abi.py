@@ -26,7 +26,8 @@ def L():
 def test_exports_every_declared_symbol(L):
     names = _declared()
     assert set(names) == {"mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_divrem_ragged",
-                          "mp_ragged_workspace_bytes", "mp_ragged_config", "mp_status_str", "mp_max_limbs"}
+                          "mp_ragged_workspace_bytes", "mp_ragged_config", "mp_set_knob", "mp_get_knob",
+                          "mp_lds_bytes", "mp_status_str", "mp_max_limbs"}
     for n in names:
         assert hasattr(L, n), n
     from paper_2606_06386_amd import binding
@@ -69,20 +70,41 @@ def test_host_argument_errors(L):
     assert L.mp_ragged_config(0, 256, 9) == MP_ERR_ARG
 
 
-def test_lds_plan_bounds():
-    """The per-instance LDS plan (mirrored here from mp_div.hpp's plan_div for
-    the host-side size check) stays within gfx950's 160 KB at 2^18 bits."""
-    from paper_2606_06386_amd import costmodel  # noqa: F401  (importable without a GPU)
-    pad, ctl, xpad = 264, 256, 16
-    r4 = lambda x: (x + 3) & ~3
-    worst = 0
-    h = 8192
-    for k in range(1, h):
-        d = h - k
-        tot = (ctl + r4(k + 1) + r4(d + 8) + r4(k + 12) + xpad + r4(h // 2 + 16) + xpad + pad
-               + r4(max(h, k + 12, d + 8) + 4) + pad + r4(max(2 * h - k + 1, h + 8) + 4) + 4)
-        worst = max(worst, tot)
-    assert worst * 4 <= 160 * 1024
+def test_lds_plan_bounds(L):
+    """The library's own LDS sizing (mp_lds_bytes, the figure every launch
+    checks) fits gfx950's 160 KB per workgroup at every width up to 2^18 bits
+    and grows with the width; wider launches are refused, not truncated."""
+    from paper_2606_06386_amd.binding import MP_OP_DIVREM, MP_OP_MUL, MP_OP_SHINV
+    lim = 160 * 1024
+    prev = 0
+    for nu in (64, 1024, 2048, 4096, 6000, 8192):
+        b = L.mp_lds_bytes(MP_OP_DIVREM, nu, nu)
+        assert prev < b <= lim, (nu, b)
+        prev = b
+        assert L.mp_lds_bytes(MP_OP_DIVREM, nu, 1) <= b
+        assert 0 < L.mp_lds_bytes(MP_OP_SHINV, nu, nu) <= lim
+    # the 2^16-bit workload keeps four workgroups per compute unit
+    assert 4 * L.mp_lds_bytes(MP_OP_DIVREM, 2048, 1024) <= lim
+    assert L.mp_lds_bytes(MP_OP_MUL, 8192, 6145) < L.mp_lds_bytes(MP_OP_MUL, 8192, 8192) <= lim
+    for bad in ((MP_OP_DIVREM, 0, 4), (MP_OP_DIVREM, 8193, 4), (MP_OP_MUL, 4, 9000), (7, 4, 4)):
+        assert L.mp_lds_bytes(*bad) == -1
+
+
+def test_knobs(L):
+    from paper_2606_06386_amd.binding import MP_ERR_ARG, MP_KNOB_MFMA_MIN, MP_KNOB_SMALL_LIMIT, MP_OK
+    m0, s0 = L.mp_get_knob(MP_KNOB_MFMA_MIN), L.mp_get_knob(MP_KNOB_SMALL_LIMIT)
+    assert m0 >= 1 and 0 <= s0 <= 256
+    try:
+        assert L.mp_set_knob(MP_KNOB_MFMA_MIN, 1 << 30) == MP_OK
+        assert L.mp_get_knob(MP_KNOB_MFMA_MIN) == 1 << 30
+        assert L.mp_set_knob(MP_KNOB_MFMA_MIN, 0) == MP_ERR_ARG
+        assert L.mp_set_knob(MP_KNOB_SMALL_LIMIT, 257) == MP_ERR_ARG
+        assert L.mp_set_knob(MP_KNOB_SMALL_LIMIT, -1) == MP_ERR_ARG
+        assert L.mp_set_knob(9, 1) == MP_ERR_ARG and L.mp_get_knob(9) == -1
+        assert L.mp_get_knob(MP_KNOB_SMALL_LIMIT) == s0
+    finally:
+        L.mp_set_knob(MP_KNOB_MFMA_MIN, m0)
+        L.mp_set_knob(MP_KNOB_SMALL_LIMIT, s0)
 
 
 def test_cost_model_values():
