@@ -137,9 +137,15 @@ mp_status_t mp_ragged_config(int32_t cls, int32_t threads, int32_t wgs_per_cu);
  *                        limbs (>= 1) run on the int8 matrix cores as exact
  *                        balanced radix-256 digit products; shorter ones on the
  *                        vector ALU (32x32->64-bit multiply-adds).  Default 64.
- *   MP_KNOB_SMALL_LIMIT  Refine iterations of Alg. 1 whose iterate has fewer
- *                        than this many limbs (0..256) run on a single wave of
- *                        the workgroup.  Default 64.
+ *   MP_KNOB_SMALL_LIMIT  Alg. 1's initial approximation and the Refine
+ *                        iterations whose iterate has fewer than this many
+ *                        limbs (0..128) run in a separate head launch, one wave
+ *                        per instance, before the per-instance workgroups do
+ *                        the rest; the head leaves its state in the first
+ *                        limbs of the instance's q (mp_shinv_batch: w) row,
+ *                        which the final result then overwrites.  0 (or an
+ *                        output row shorter than 16 limbs) runs every step in
+ *                        the per-instance workgroups.  Default 64.
  * mp_set_knob returns MP_ERR_ARG for an unknown knob or a value out of range;
  * mp_get_knob returns the current value (-1 for an unknown knob).
  */

@@ -3,7 +3,7 @@
 Compiles the sources in csrc/ for gfx950 with hipcc into libmpdiv.so next to
 this file (in-tree, so the built library travels with the source tree).
 kernels.hip is compiled once per kernel family and workgroup size (each
-object holds one launcher and its kernel), and all objects are compiled in
+object holds one launcher and its kernel) and once for the head kernels, and all objects are compiled in
 parallel, then linked with the host API (mpdiv.hip).
 """
 import os
@@ -24,7 +24,7 @@ HEADERS = [os.path.join(CSRC, f) for f in ("mp_prims_hip.hpp", "mp_core.hpp", "m
 # (object name, source, defines): one object per kernel family x workgroup size
 FAMILIES = {0: "mul", 1: "shinv", 2: "divrem", 3: "ragged"}
 THREADS = (256, 512, 1024)
-UNITS = [("api", "mpdiv.hip", [])] + [
+UNITS = [("api", "mpdiv.hip", []), ("k_head", "kernels.hip", ["-DMP_KFAMILY=4", "-DMP_KT=64"])] + [
     (f"k_{name}_{t}", "kernels.hip", [f"-DMP_KFAMILY={fam}", f"-DMP_KT={t}"])
     for fam, name in FAMILIES.items() for t in THREADS]
 

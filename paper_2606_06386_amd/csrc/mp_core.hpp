@@ -28,6 +28,7 @@ constexpr int kRCol = 4;                 // product columns per lane
 constexpr int kStrip = kLanes * kRCol;   // product columns per wave pass
 constexpr int kPad = kStrip + 8;         // zero guard on both sides of a staged window operand
 constexpr int kCMax = 17;                // most limbs one thread handles in a linear operation
+constexpr int kHeadMaxLimbs = 9 * kLanes;   // longest operand of a one-wave addsub (9 limbs per lane)
 
 // control block at the start of the instance's LDS (32-bit words)
 constexpr int kCtlRed = 0;       // 3 x 16 per-wave reduction slots
@@ -133,7 +134,7 @@ MP_DEV uint32_t wg_max(uint32_t *ctl, uint32_t x)
     constexpr int W = T / kLanes;
     x = wave_max(x);
     if constexpr (W == 1) return uniform(x);
-    if (lane() == 0) ctl[kCtlRed + tid() / kLanes] = x;
+    if (lane() == 0) ctl[kCtlRed + tid<T>() / kLanes] = x;
     bar<T>();
     uint32_t r = 0;
 #pragma unroll
@@ -149,7 +150,7 @@ template <int T, int N>
 MP_DEV void wg_max_n(uint32_t *ctl, uint32_t (&x)[N])
 {
     constexpr int W = T / kLanes;
-    const int w = uniform(tid() / kLanes);
+    const int w = uniform(tid<T>() / kLanes);
 #pragma unroll
     for (int i = 0; i < N; i++) {
         const uint32_t m = wave_max(x[i]);
@@ -177,7 +178,7 @@ MP_DEV int reduce_max(uint32_t *ctl, int n, const F &f)
 {
     bar<T>();
     uint32_t m = 0;
-    int k = tid();
+    int k = tid<T>();
     for (; k + 3 * T < n; k += 4 * T) {
         const uint32_t y0 = f(k), y1 = f(k + T), y2 = f(k + 2 * T), y3 = f(k + 3 * T);
         m = umax(m, umax(umax(y0, y1), umax(y2, y3)));
@@ -226,7 +227,7 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
     constexpr int W = T / kLanes;
     constexpr bool kPre = CM <= 9;   // short chunks: all reads first, so their latencies overlap
     constexpr int CP = kPre ? CM : 1;
-    const int k0 = tid() * C;
+    const int k0 = tid<T>() * C;
     uint32_t z[CM], av[CP], bv[CP];
     uint32_t c = 0;
     bool prop = true;
@@ -259,7 +260,7 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
     }
     const uint64_t G = ballot(c != 0), P = ballot(prop), X = G | P;
     const uint64_t s0 = X + G;
-    const int w = uniform(tid() / kLanes);
+    const int w = uniform(tid<T>() / kLanes);
     uint32_t cin_w = cin, cout = cin;
     if constexpr (W == 1) {
         // one wave: its own summary is the whole scan
@@ -330,8 +331,13 @@ MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
     if (C == 1) return addsub_chunk<T, 1>(ctl, n, C, sub, cin, x, y, out);
     if (C == 3) return addsub_chunk<T, 3>(ctl, n, C, sub, cin, x, y, out);
     if (C <= 5) return addsub_chunk<T, 5>(ctl, n, C, sub, cin, x, y, out);
-    if (C <= 9) return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out);
-    return addsub_chunk<T, kCMax>(ctl, n, C, sub, cin, x, y, out);
+    // a single wave (a head) handles at most kHeadMaxLimbs limbs per operation
+    if constexpr (T == kLanes) {
+        return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out);
+    } else {
+        if (C <= 9) return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out);
+        return addsub_chunk<T, kCMax>(ctl, n, C, sub, cin, x, y, out);
+    }
 }
 
 // dst[k] = src(k) for k in [0, n), zero for k in [n, clear)
@@ -340,7 +346,7 @@ MP_DEV void copy(uint32_t *dst, int n, int clear, const FS &src)
 {
     bar<T>();
     const int e = imax(n, clear);
-    int k = tid();
+    int k = tid<T>();
     for (; k + 3 * T < e; k += 4 * T) {
         const uint32_t y0 = k < n ? src(k) : 0u, y1 = k + T < n ? src(k + T) : 0u;
         const uint32_t y2 = k + 2 * T < n ? src(k + 2 * T) : 0u, y3 = k + 3 * T < n ? src(k + 3 * T) : 0u;
@@ -461,12 +467,12 @@ MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
     constexpr int W = T / kLanes;
     bar<T>();
     if (na == 0 || nb == 0 || ncols <= c0) {
-        for (int k = c0 + tid(); k < ncols; k += T) p[k] = 0u;
+        for (int k = c0 + tid<T>(); k < ncols; k += T) p[k] = 0u;
         return 0;
     }
     const int nstrips = (ncols - c0 + kStrip - 1) / kStrip;
     const int base = strip_base(c0, ncols, na + nb, nstrips);
-    const int w = uniform(tid() / kLanes), l = lane();
+    const int w = uniform(tid<T>() / kLanes), l = lane();
     for (int s = w; s < nstrips; s += W) {
         const int K0 = base + s * kStrip, k0 = K0 + l * kRCol;
         const int ilo = imax(0, K0 - nb + 1) & ~3;
@@ -576,12 +582,12 @@ MP_DEV void mfma_operands(uint32_t *ctl, const FY &y, int ny, uint32_t *yb, int 
                           const FX &x, int nx, uint32_t *xr)
 {
     bar<T>();
-    for (int k = ny + 1 + tid(); k < yclear; k += T) yb[k] = 0u;
+    for (int k = ny + 1 + tid<T>(); k < yclear; k += T) yb[k] = 0u;
     addsub<T>(ctl, ny + 1, false, 0u, y, Bal80{ny}, StoreBal{yb, ny});
     addsub<T>(ctl, nx + 1, false, 0u, x, Bal80{nx}, StoreBalRev{xr, nx});
     // every read of x happened before addsub's internal barrier, and the pads
     // are disjoint from the digits written: no barrier needed here
-    for (int k = tid(); k < 2 * kXPad; k += T) {
+    for (int k = tid<T>(); k < 2 * kXPad; k += T) {
         if (k < kXPad) xr[k - kXPad] = 0u;
         else xr[nx + 1 + k - kXPad] = 0u;
     }
@@ -602,7 +608,7 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
     if (ncols <= c0) return 0;
     const int nstrips = (ncols - c0 + kStrip - 1) / kStrip;
     const int base = strip_base(c0, ncols, nx + ny, nstrips);
-    const int w = uniform(tid() / kLanes), l = lane();
+    const int w = uniform(tid<T>() / kLanes), l = lane();
     const int t = l & 31, h = l >> 5;
     const int nyblk = (ny + 1 + 7) >> 3;          // 32-byte blocks of the long digits
     const int R0 = 4 * (nx + 1) - 1;              // reversed byte x holds digit R0 - x
@@ -680,7 +686,7 @@ MP_DEV uint32_t shortdiv(uint32_t *ctl, uint32_t *scratch, int n, const FD &d, u
     bar<T>();
     const int C = imax((n + T - 1) / T, imin(n, 64));
     const int nch = (n + C - 1) / C;
-    const int t = tid(), k0 = t * C;
+    const int t = tid<T>(), k0 = t * C;
     if (t < nch) {
         uint64_t r = 0;
         for (int j = C - 1; j >= 0; j--) {

@@ -17,9 +17,21 @@
 //     h-k-1 <= 1;
 //   * Step's rounding test looks at the h-2m (not 2m-h) low limbs of w*x;
 //   * PowDiff's sign is 1 iff B^h - v*w >= 0;
-//   * the computed inverse can be floor(B^h/v) - 1 as well as + 1, so the
-//     division allows one downward and two upward quotient corrections, and
-//     the stand-alone shinv ends with an exact one-step fix-up.
+//   * the computed inverse can be floor(B^h/v) - 1 as well as + 1, and the
+//     clipped products below move it by at most one more unit either way, so
+//     the division corrects q0 by up to four subtractions and five additions
+//     of v (q - 4 <= q0 <= q + 3 is what the bound allows; one more step
+//     each way is a safety margin that reports INTERNAL instead of a wrong
+//     answer), and the stand-alone shinv ends with an exact fix-up.
+//
+// Two kernels share the work of one instance.  The head (one wave per
+// instance, many instances per compute unit) computes the initial
+// approximation and the early Refine iterations, whose operands are short;
+// it leaves their state in a record at the start of the instance's own output
+// row (q for a division, w for a shifted inverse).  The body (one workgroup
+// per instance) picks the record up and runs the remaining iterations and
+// the quotient and remainder products.  Without a record the body runs every
+// step itself.
 #pragma once
 
 #include <stdint.h>
@@ -44,12 +56,14 @@ MP_HD int hmax(int a, int b) { return a > b ? a : b; }
 struct Plan {
     int capV, capW, capX, capR, capSB, capP;
     int offV, offW, offX, offR, offSB, offP;   // offR: word 0 of the reversed digits, offSB: limb 0 of the window
+    int vbase;                                 // index of the divisor limb stored at offV (limbs below are not held)
     int total;
 };
 
 MP_HD Plan plan_div(int h, int k)
 {
     Plan p;
+    p.vbase = 0;
     const int d = h - k;
     p.capV = r4(k + 1);
     p.capW = r4(d + 8);
@@ -66,6 +80,48 @@ MP_HD Plan plan_div(int h, int k)
     p.total = p.offP + p.capP + 4;
     return p;
 }
+
+// LDS layout of one wave's head (the Refine iterations whose iterate has fewer
+// than `limit` limbs, so l <= limit - 4): the divisor limbs [vbase, k] it
+// reads (v' = v >> s has at most 2l + 2 limbs), the iterate (at most 2l + 2
+// limbs after the last of these iterations), PowDiff's residual (at most
+// 3l + 3 limbs, B^h' minus a product), the window operand with its zero
+// guards, and products (w * x: at most 4l + 9 limbs).  No matrix-core area:
+// operands this short run on the vector ALU.  Every use is guarded; an
+// iteration that would overrun returns false and the body does it instead.
+constexpr int kHeadMaxLimit = 128;   // largest small_limit: every head operand then fits kHeadMaxLimbs
+// (the longest one-wave linear operation of a head is bounded by capP, capX or
+// capW + l, all below 4 * limit + 8 limbs)
+static_assert(4 * kHeadMaxLimit + 8 <= kHeadMaxLimbs, "head operands must fit one wave's addsub");
+
+MP_HD Plan plan_head(int limit, int vbase)
+{
+    Plan p;
+    const int L = limit < 4 ? 4 : limit > kHeadMaxLimit ? kHeadMaxLimit : limit;
+    p.vbase = vbase;
+    p.capV = r4(2 * L);
+    p.capW = r4(2 * L + 8);
+    p.capX = r4(3 * L + 8);
+    p.capR = 0;
+    p.capSB = r4(3 * L + 8);
+    p.capP = r4(4 * L + 8);
+    p.offV = kCtlWords;
+    p.offW = p.offV + p.capV;
+    p.offX = p.offW + p.capW;
+    p.offR = p.offX + p.capX + kXPad;
+    p.offSB = p.offR + kXPad + kPad;
+    p.offP = p.offSB + p.capSB + kPad;
+    p.total = p.offP + p.capP + 4;
+    return p;
+}
+
+// Record of the head in the instance's output row (32-bit words):
+//   [0] kRecValid, or 0 when the body is to do every step itself
+//   [1] Refine iterations done   [2] l   [3] we   [4] nw   [5] h   [6] k
+//   [kRecHdr, kRecHdr + we) the limbs of the iterate W
+constexpr uint32_t kRecValid = 0x52454331u;
+constexpr int kRecHdr = 8;
+constexpr int kHeadWaves = 4;   // head instances (waves) per workgroup
 
 // words needed by the single-limb-divisor path (quotient + chunk scratch)
 MP_HD int plan_short_words(int n, int T) { return kCtlWords + 2 * T + r4(n + 1) + 4; }
@@ -94,30 +150,35 @@ MP_HD int mul_lds_words(int na, int nb)
 // digits in sb, short operand's reversed digits in xr, which holds xrcap
 // limbs); the rest walk the rows on the VALU with the longer operand staged in
 // sb as window.
-template <int T, class FL, class FS>
+//
+// MF = false builds the vector-ALU path only (for code that never has an
+// operand long enough for the matrix cores).
+template <int T, bool MF, class FL, class FS>
 MP_DEV int product_views(uint32_t *ctl, uint32_t *p, int ncols, const FL &lng, int nl, const uint32_t *lng_lds,
                          const FS &sht, int ns, const uint32_t *sht_lds, uint32_t *sb, int &sbext,
                          uint32_t *xr, int xrcap, int mfma_min, int c0 = 0, bool want_prec = true)
 {
-    if (ns >= mfma_min && ns + 1 <= xrcap) {
-        mfma_operands<T>(ctl, lng, nl, sb, sbext, sht, ns, xr);
-        sbext = nl + 1;
-        return mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0, want_prec);
+    if constexpr (MF) {
+        if (ns >= mfma_min && ns + 1 <= xrcap) {
+            mfma_operands<T>(ctl, lng, nl, sb, sbext, sht, ns, xr);
+            sbext = nl + 1;
+            return mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0, want_prec);
+        }
     }
     copy<T>(sb, nl, sbext, lng);
     sbext = nl;
     return mul<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0, want_prec);
 }
 
-template <int T>
+template <int T, bool MF = true>
 MP_DEV int product(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *x, int nx,
                    const uint32_t *y, int ny, uint32_t *sb, int &sbext, uint32_t *xr, int xrcap, int mfma_min,
                    int c0 = 0, bool want_prec = true)
 {
     const uint32_t *sht = nx >= ny ? y : x, *lng = nx >= ny ? x : y;
     const int ns = nx >= ny ? ny : nx, nl = nx >= ny ? nx : ny;
-    return product_views<T>(ctl, p, ncols, Span{lng, 0, nl}, nl, lng, Span{sht, 0, ns}, ns, sht, sb, sbext,
-                            xr, xrcap, mfma_min, c0, want_prec);
+    return product_views<T, MF>(ctl, p, ncols, Span{lng, 0, nl}, nl, lng, Span{sht, 0, ns}, ns, sht, sb, sbext,
+                                xr, xrcap, mfma_min, c0, want_prec);
 }
 
 // dst[0, n) = src limbs [0, e) zero-padded, where e = prec(src) must be <= n;
@@ -127,7 +188,7 @@ MP_DEV bool store_fit(uint32_t *ctl, uint32_t *dst, int n, int ext, const FS &sr
 {
     const int e = prec<T>(ctl, ext, src);
     if (e > n) return false;
-    int i = tid();
+    int i = tid<T>();
     for (; i + 3 * T < n; i += 4 * T) {
         const uint32_t y0 = i < e ? src(i) : 0u, y1 = i + T < e ? src(i + T) : 0u;
         const uint32_t y2 = i + 2 * T < e ? src(i + 2 * T) : 0u, y3 = i + 3 * T < e ? src(i + 3 * T) : 0u;
@@ -143,22 +204,15 @@ MP_DEV bool store_fit(uint32_t *ctl, uint32_t *dst, int n, int ext, const FS &sr
 template <int T>
 MP_DEV void store_zero(uint32_t *dst, int n)
 {
-    for (int i = tid(); i < n; i += T) dst[i] = 0u;
-}
-
-MP_DEV int ceil_log2(int x)   // x >= 1
-{
-    int r = 0;
-    while ((1 << r) < x) r++;
-    return r;
+    for (int i = tid<T>(); i < n; i += T) dst[i] = 0u;
 }
 
 // ------------------------------------------------------- Alg. 1 Refine
 
 // Iteration i of the Refine loop (Alg. 1): PowDiff, then Step, updating the
 // iterate W (nonzero limbs inside [0, we), precision nw) and l.  Run by T
-// threads (the workgroup, or one wave for the small early iterations).
-template <int T>
+// threads (the workgroup, or one wave in a head); MF as for product_views.
+template <int T, bool MF = true>
 MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t *lds, int h, int k, int i, int &l,
                         int &we, int &nw, int &sbext)
 {
@@ -168,7 +222,8 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
     const int m = imin(d + 1 - l, l);
     const int s = imax(0, k - 2 * l + 1 - g);
     const int H = k + l + m - s + g;
-    const uint32_t *vp = V + s;          // divisor prefix shift_{-s}(v)
+    if (s < pl.vbase) return false;      // (a head holds only the limbs its iterations read)
+    const uint32_t *vp = V + (s - pl.vbase);   // divisor prefix shift_{-s}(v)
     const int nvp = k + 1 - s;
     const int hp = H - m, lp = l - g;   // PowDiff(v', w, H - m, l - g)
     const int L = nvp + nw - lp + 1;
@@ -177,7 +232,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
     if (L >= hp) {                      // full product, compare with B^hp
         const int np0 = nvp + nw;
         if (np0 > pl.capP) return false;
-        const int np = product<T>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR, kn.mfma_min);
+        const int np = product<T, MF>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR, kn.mfma_min);
         if (np <= hp) {                 // P < B^hp: x = B^hp - P
             if (hp > pl.capX) return false;
             sign = true;
@@ -190,7 +245,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
         nx = read_prec<T>(ctl);
     } else {                            // close product: P = v'w mod B^L
         if (L > pl.capP || L > pl.capX) return false;
-        const int np = product<T>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR, kn.mfma_min);
+        const int np = product<T, MF>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR, kn.mfma_min);
         if (np == 0) {                  // v'w = B^hp exactly
             sign = true;
             nx = 0;
@@ -221,7 +276,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
         cs = nt >= sh + 2 ? imax(sh - 2, 0) & ~7 : 0;
         if (cs) nt += 1;
         if (nt > pl.capP) return false;
-        product<T>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, kn.mfma_min, cs, false);
+        product<T, MF>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, kn.mfma_min, cs, false);
     }
     uint32_t sticky = 0;
     if (!sign && nt > cs) {
@@ -239,23 +294,39 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
     return true;
 }
 
-// Initial approximation and the Refine loop for B^k <= v < B^(k+1), k >= 1,
-// h - k >= 1, B < v <= B^h / 2, v not a power of B.  v is in V (k+1 limbs).
-// On return the shifted inverse is the limbs of W above `shf`; W's nonzero
-// limbs lie inside [0, we) and nw = prec(W).  Returns false if a capacity
-// guard trips or a Step result turns negative (never expected).  The early
-// iterations, whose iterate is shorter than kn.small_limit limbs, run on the
-// first wave alone (no workgroup barriers) while the others wait.
-template <int T>
-MP_DEV bool refine(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t *lds, int h, int k, int &we, int &nw,
-                   int &shf, int &sbext)
+MP_HD int refine_iters(int d)   // Alg. 1's iteration count for h - k = d >= 1
 {
-    uint32_t *V = lds + pl.offV, *W = lds + pl.offW;
-    const int g = 2, d = h - k;
-    // w = shift_g(floor(B^3 / V)), V = v_{k-1} + v_k B; w0 <= B^2 has 3 limbs
+    int r = 0;
+    while (d - 1 > 1 && (1 << r) < d - 1) r++;
+    return 2 + r;
+}
+
+// l at the start of Refine iteration i (d = h - k)
+MP_HD int refine_l(int d, int i)
+{
+    int l = 2;
+    for (int j = 2; j < i; j++) l = l + (d + 1 - l < l ? d + 1 - l : l) - 1;
+    return l;
+}
+
+// number of leading Refine iterations whose iterate (l + g + 1 limbs) is
+// shorter than `limit` limbs
+MP_HD int small_iters(int d, int limit)
+{
+    const int iters = refine_iters(d);
+    int n = 0;
+    while (n < iters && refine_l(d, n) + 3 < limit) n++;
+    return n;
+}
+
+// Alg. 1's initial approximation w = shift_g(floor(B^3 / V)), V = v_{k-1} + v_k B:
+// w0 <= B^2 has 3 limbs (65 bits when V = B).  vtop points at v_{k-1}, v_k.
+template <int T>
+MP_DEV void refine_init(uint32_t *ctl, const uint32_t *vtop, uint32_t *W, int &we, int &nw)
+{
     bar<T>();
-    if (tid() == 0) {
-        const uint64_t Vt = ((uint64_t)V[k] << 32) | V[k - 1];
+    if (tid<T>() == 0) {
+        const uint64_t Vt = ((uint64_t)vtop[1] << 32) | vtop[0];
         const unsigned __int128 w0 = (((unsigned __int128)1) << 96) / Vt;
         W[0] = 0u;
         W[1] = 0u;
@@ -265,45 +336,130 @@ MP_DEV bool refine(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t *lds
         ctl[kCtlBcast + 1] = W[4] ? 5u : W[3] ? 4u : 3u;
     }
     bar<T>();
-    MP_STAMP(3);
     nw = (int)uniform(ctl[kCtlBcast + 1]);
     we = 5;
-    int l = 2;
-    const int iters = 2 + (d - 1 <= 1 ? 0 : ceil_log2(d - 1));
-    int i = 0;
-    if constexpr (T > kLanes) {
-        int nsmall = 0;                       // iterations with an iterate of l + g + 1 < small_limit limbs
-        for (int ll = 2; nsmall < iters && ll + g + 1 < kn.small_limit; nsmall++)
-            if (nsmall >= 2) ll = ll + imin(d + 1 - ll, ll) - 1;
-        if (nsmall > 0) {
-            if (tid() < kLanes) {
-                bool ok = true;
-                int l1 = l, we1 = we, nw1 = nw, sb1 = sbext;
-                for (int j = 0; j < nsmall && ok; j++) ok = refine_iter<kLanes>(ctl, pl, kn, lds, h, k, j, l1, we1, nw1, sb1);
-                if (tid() == 0) {
-                    ctl[kCtlBcast + 3] = ok ? 1u : 0u;
-                    ctl[kCtlBcast + 4] = (uint32_t)l1;
-                    ctl[kCtlBcast + 5] = (uint32_t)we1;
-                    ctl[kCtlBcast + 6] = (uint32_t)nw1;
-                    ctl[kCtlBcast + 7] = (uint32_t)sb1;
-                }
-            }
-            sync();
-            MP_STAMP(4);
-            if (!uniform(ctl[kCtlBcast + 3])) return false;
-            l = (int)uniform(ctl[kCtlBcast + 4]);
-            we = (int)uniform(ctl[kCtlBcast + 5]);
-            nw = (int)uniform(ctl[kCtlBcast + 6]);
-            sbext = (int)uniform(ctl[kCtlBcast + 7]);
-            i = nsmall;
-        }
+}
+
+// Initial approximation and the Refine loop for B^k <= v < B^(k+1), k >= 1,
+// h - k >= 1, B < v <= B^h / 2, v not a power of B.  v is in V (k+1 limbs),
+// W and the window area are zero.  With a valid head record `rec` (in global
+// memory) the iterations it covers are taken from it instead.  On return the
+// shifted inverse is the limbs of W above `shf`; W's nonzero limbs lie inside
+// [0, we) and nw = prec(W).  Returns false if a capacity guard trips or a
+// Step result turns negative (never expected).
+template <int T>
+MP_DEV bool refine(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t *lds, int h, int k, int &we, int &nw,
+                   int &shf, int &sbext, const uint32_t *rec)
+{
+    uint32_t *V = lds + pl.offV, *W = lds + pl.offW;
+    const int d = h - k;
+    const int iters = refine_iters(d);
+    int l = 2, i = 0;
+    if (rec) {
+        i = (int)uniform(rec[1]);
+        l = (int)uniform(rec[2]);
+        we = (int)uniform(rec[3]);
+        nw = (int)uniform(rec[4]);
+        if (we > pl.capW) return false;
+        copy<T>(W, we, 0, Span{rec + kRecHdr, 0, we});
+    } else {
+        refine_init<T>(ctl, V + k - 1, W, we, nw);
     }
+    MP_STAMP(3);
+    MP_STAMP(4);
     for (; i < iters; i++) {
         if (!refine_iter<T>(ctl, pl, kn, lds, h, k, i, l, we, nw, sbext)) return false;
         MP_STAMP(16 + (i & 15));
     }
     shf = d < 2 ? 4 - d : 2;
     return true;
+}
+
+// ------------------------------------------------------------------- head
+
+// number of significant limbs of x[0, n) (global memory), by one wave from the top
+MP_DEV int wave_prec(const uint32_t *x, int n)
+{
+    for (int top = n; top > 0; top -= kLanes) {
+        const int i = top - kLanes + lane();
+        const uint64_t m = ballot(i >= 0 && x[i] != 0u);
+        if (m) return top - kLanes + 64 - __builtin_clzll(m);
+    }
+    return 0;
+}
+
+// index of the lowest nonzero limb of x[0, n) (n when there is none), by one wave
+MP_DEV int wave_low(const uint32_t *x, int n)
+{
+    for (int base = 0; base < n; base += kLanes) {
+        const int i = base + lane();
+        const uint64_t m = ballot(i < n && x[i] != 0u);
+        if (m) return base + __builtin_ctzll(m);
+    }
+    return n;
+}
+
+// The head of one instance with h and k = prec(v) - 1, by one wave in its own
+// LDS area (plan_head words): for the general case with h - k >= 2 and v not a
+// power of B, Alg. 1's initial approximation and its Refine iterations while
+// the iterate is shorter than kn.small_limit limbs, recorded in rec[0, nrec);
+// otherwise (or when the state does not fit) rec[0] = 0.
+MP_DEV void head_refine(uint32_t *lds, int h, const uint32_t *v, int nv, uint32_t *rec, int nrec, const Knobs &kn)
+{
+    constexpr int T = kLanes;
+    uint32_t *ctl = lds;
+    const int k = wave_prec(v, nv) - 1, d = h - k, g = 2;
+    bool go = k >= 1 && d >= 2;
+    if (go) go = !(wave_low(v, k + 1) == k && v[k] == 1u);
+    const int ns = go ? small_iters(d, kn.small_limit) : 0;
+    const int vbase = ns ? imax(0, k - 2 * refine_l(d, ns - 1) + 1 - g) : 0;
+    const Plan pl = plan_head(kn.small_limit, vbase);
+    if (ns == 0 || k + 1 - vbase > pl.capV) {
+        if (lane() == 0) rec[0] = 0u;
+        return;
+    }
+    uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *SB = lds + pl.offSB;
+    for (int i = lane(); i < k + 1 - vbase; i += T) V[i] = v[vbase + i];
+    for (int i = lane(); i < pl.capW; i += T) W[i] = 0u;
+    for (int i = lane() - kPad; i < pl.capSB + kPad; i += T) SB[i] = 0u;
+    int we = 0, nw = 0, sbext = 0, l = 2;
+    refine_init<T>(ctl, V + (k - 1 - vbase), W, we, nw);
+    bool ok = true;
+    for (int i = 0; i < ns && ok; i++) ok = refine_iter<T, false>(ctl, pl, kn, lds, h, k, i, l, we, nw, sbext);
+    ok = ok && kRecHdr + we <= nrec;
+    wave_sync();
+    if (!ok) {
+        if (lane() == 0) rec[0] = 0u;
+        return;
+    }
+    for (int i = lane(); i < we; i += T) rec[kRecHdr + i] = W[i];
+    if (lane() == 0) {
+        rec[1] = (uint32_t)ns;
+        rec[2] = (uint32_t)l;
+        rec[3] = (uint32_t)we;
+        rec[4] = (uint32_t)nw;
+        rec[5] = (uint32_t)h;
+        rec[6] = (uint32_t)k;
+        rec[7] = 0u;
+        rec[0] = kRecValid;
+    }
+}
+
+// the head of a division (h = prec(u))
+MP_DEV void head_divrem(uint32_t *lds, const uint32_t *u, int nu, const uint32_t *v, int nv, uint32_t *rec, int nrec,
+                        const Knobs &kn)
+{
+    head_refine(lds, wave_prec(u, nu), v, nv, rec, nrec, kn);
+}
+
+// a head record for (h, k) in the output row rec[0, nrec), or nullptr when rec
+// is absent or holds none (a valid record always fits its row)
+template <int T>
+MP_DEV const uint32_t *head_record(const uint32_t *rec, int nrec, int h, int k)
+{
+    if (!rec || nrec < kRecHdr) return nullptr;
+    if (uniform(rec[0]) != kRecValid) return nullptr;
+    return (int)uniform(rec[5]) == h && (int)uniform(rec[6]) == k ? rec : nullptr;
 }
 
 // ------------------------------------------------------------ instances
@@ -332,13 +488,14 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
     }
     (void)np;
     bar<T>();
-    for (int i = tid(); i < na + nb; i += T) c[i] = P[i];
+    for (int i = tid<T>(); i < na + nb; i += T) c[i] = P[i];
 }
 
-// w = floor(B^h / v), exactly (nw limbs)
+// w = floor(B^h / v), exactly (nw limbs).  rec: the head's record (at w), or
+// nullptr when no head ran
 template <int T>
 MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint32_t *w, int nw,
-                           int32_t *status, const Knobs &kn)
+                           int32_t *status, const Knobs &kn, const uint32_t *rec)
 {
     uint32_t *ctl = lds;
     const Span Vg{v, 0, nv};
@@ -346,7 +503,7 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
     const int nvv = prec<T>(ctl, nv, Vg);
     if (nvv == 0) {
         store_zero<T>(w, nw);
-        if (status && tid() == 0) *status = kInstDivZero;
+        if (status && tid<T>() == 0) *status = kInstDivZero;
         return;
     }
     const int k = nvv - 1;
@@ -363,12 +520,12 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
                (k == h - 1 && (vk > 0x80000000u || (vk == 0x80000000u && !lowz)))) {  // 2v > B^h
         ok = nw >= 1;
         if (ok)
-            for (int i = tid(); i < nw; i += T) w[i] = i == 0 ? 1u : 0u;
+            for (int i = tid<T>(); i < nw; i += T) w[i] = i == 0 ? 1u : 0u;
     } else if (lowz && vk == 1u) {                            // v = B^k: B^(h-k)
         ok = nw > h - k;
         if (ok) {
             const int e = h - k;
-            for (int i = tid(); i < nw; i += T) w[i] = i == e ? 1u : 0u;
+            for (int i = tid<T>(); i < nw; i += T) w[i] = i == e ? 1u : 0u;
         }
     } else {
         const Plan pl = plan_div(h, k);
@@ -378,7 +535,7 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
         copy<T>(W, 0, pl.capW, Zero{});
         copy<T>(SB - kPad, 0, pl.capSB + 2 * kPad, Zero{});
         int we = 0, nwi = 0, shf = 0, sbext = 0;
-        if (!refine<T>(ctl, pl, kn, lds, h, k, we, nwi, shf, sbext)) {
+        if (!refine<T>(ctl, pl, kn, lds, h, k, we, nwi, shf, sbext, head_record<T>(rec, nw, h, k))) {
             st = kInstInternal;
         } else {
             // exact fix-up: D = B^h - v s with s within two of floor(B^h/v), so
@@ -426,13 +583,15 @@ MP_DEV void shinv_instance(uint32_t *lds, const uint32_t *v, int nv, int h, uint
         bar<T>();
         store_zero<T>(w, nw);
     }
-    if (status && tid() == 0) *status = st;
+    if (status && tid<T>() == 0) *status = st;
 }
 
-// (q, r) with u = q v + r, 0 <= r < v  (q: nq limbs, r: nv limbs)
+// (q, r) with u = q v + r, 0 <= r < v  (q: nq limbs, r: nv limbs).  rec: the
+// head's record (at q), or nullptr when no head ran
 template <int T>
 MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint32_t *v, int nv,
-                            uint32_t *q, int nq, uint32_t *r, int32_t *status, const Knobs &kn)
+                            uint32_t *q, int nq, uint32_t *r, int32_t *status, const Knobs &kn,
+                            const uint32_t *rec)
 {
     uint32_t *ctl = lds;
     const Span Ug{u, 0, nu}, Vg{v, 0, nv};
@@ -449,7 +608,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         // holds kCtlWords + nu words)
         uint32_t *V0 = lds + kCtlWords;
         const int nm = nu > nv ? nu : nv, nvs = nu < nv ? nu : nv;
-        for (int i0 = tid(); i0 < nm; i0 += 8 * T) {
+        for (int i0 = tid<T>(); i0 < nm; i0 += 8 * T) {
             uint32_t ua[8], va[8];
 #pragma unroll
             for (int j = 0; j < 8; j++) {
@@ -475,15 +634,15 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     if (nvv == 0) {
         store_zero<T>(q, nq);
         store_zero<T>(r, nv);
-        if (status && tid() == 0) *status = kInstDivZero;
+        if (status && tid<T>() == 0) *status = kInstDivZero;
         return;
     }
     const int c0 = h < nvv ? -1 : (h > nvv ? 1 : cmp<T>(ctl, h, Ug, Vg));
     const int k = nvv - 1;
     if (c0 < 0) {                                 // u < v: (0, u)
         store_zero<T>(q, nq);
-        for (int i = tid(); i < nv; i += T) r[i] = i < h ? u[i] : 0u;
-        if (status && tid() == 0) *status = kInstOk;
+        for (int i = tid<T>(); i < nv; i += T) r[i] = i < h ? u[i] : 0u;
+        if (status && tid<T>() == 0) *status = kInstOk;
         return;
     }
     const uint32_t vk = lds[kCtlWords + k];      // k < nvv <= h <= nu: stored by the first pass
@@ -493,11 +652,11 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         const uint32_t rem = shortdiv<T>(ctl, scratch, h, Ug, vk, Store{Q, 0, h});
         ok = store_fit<T>(ctl, q, nq, h, Span{Q, 0, h});
         if (ok)
-            for (int i = tid(); i < nv; i += T) r[i] = i == 0 ? rem : 0u;
+            for (int i = tid<T>(); i < nv; i += T) r[i] = i == 0 ? rem : 0u;
     } else if (lowz && vk == 1u) {                // v = B^k: shinv = B^(h-k), q = u >> k
         ok = store_fit<T>(ctl, q, nq, h - k, Span{u, -k, h});
         if (ok)
-            for (int i = tid(); i < nv; i += T) r[i] = i < k ? u[i] : 0u;
+            for (int i = tid<T>(); i < nv; i += T) r[i] = i < k ? u[i] : 0u;
     } else {
         const Plan pl = plan_div(h, k);
         uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *X = lds + pl.offX;
@@ -509,12 +668,12 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         bool good = true;
         if (k == h - 1 && (vk > 0x80000000u || (vk == 0x80000000u && !lowz))) {
             bar<T>();                               // 2v > B^h: shinv = 1
-            if (tid() == 0) W[0] = 1u;
+            if (tid<T>() == 0) W[0] = 1u;
             we = 1;
             nw = 1;
             shf = 0;
         } else {
-            good = refine<T>(ctl, pl, kn, lds, h, k, we, nw, shf, sbext);
+            good = refine<T>(ctl, pl, kn, lds, h, k, we, nw, shf, sbext, head_record<T>(rec, nq, h, k));
         }
         if (good) {
             // q0 = shift_{-h}(u * s)
@@ -527,7 +686,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
                 // limbs are floor(u s / B^h) or one less (one more on the matrix
                 // cores, whose digit products below c0 may be negative)
                 const int c0 = imax(h - 2, 0) & ~7;
-                const int np = product_views<T>(ctl, P, h + ns, Ug, h, nullptr, Span{S, 0, ns}, ns, S, SB, sbext,
+                const int np = product_views<T, true>(ctl, P, h + ns, Ug, h, nullptr, Span{S, 0, ns}, ns, S, SB, sbext,
                                                 XR, pl.capR, kn.mfma_min, c0);
                 MP_STAMP(5);
                 const int nq0 = imax(np - h, 0);
@@ -571,7 +730,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
                 if (good) {
                     ok = store_fit<T>(ctl, q, nq, we, Span{W, 0, we});
                     if (ok)
-                        for (int i = tid(); i < nv; i += T) r[i] = i < k + 1 ? R[i] : 0u;
+                        for (int i = tid<T>(); i < nv; i += T) r[i] = i < k + 1 ? R[i] : 0u;
                 }
             }
         }
@@ -583,7 +742,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
         store_zero<T>(q, nq);
         store_zero<T>(r, nv);
     }
-    if (status && tid() == 0) *status = st;
+    if (status && tid<T>() == 0) *status = st;
     MP_STAMP(8);
 }
 

@@ -31,8 +31,16 @@ namespace mp {
 
 constexpr int kLanes = 64;  // CDNA wavefront width
 
-MP_DEV int tid() { return (int)threadIdx.x; }
 MP_DEV int lane() { return (int)(threadIdx.x & (kLanes - 1)); }
+// index of the calling thread among the T threads working on one instance:
+// the workgroup's thread index, or the lane when a single wave owns the
+// instance (that wave may be any wave of its workgroup)
+template <int T>
+MP_DEV int tid()
+{
+    if constexpr (T == kLanes) return lane();
+    else return (int)threadIdx.x;
+}
 MP_DEV void sync() { __syncthreads(); }
 // orders this wave's LDS accesses before and after it (a wave runs in
 // lockstep and the LDS serves one wave's requests in order; only the

@@ -22,6 +22,11 @@ std::atomic<int32_t> g_mfma_min{64}, g_small_limit{64};
 
 mp::Knobs knobs() { return mp::Knobs{g_mfma_min.load(), g_small_limit.load()}; }
 
+// a head kernel runs first when it has iterations to do and an output row can
+// hold a record with at least a few limbs (rows too short get none and the
+// body does every step)
+int use_head(const mp::Knobs &kn, int row) { return kn.small_limit > 0 && row >= mp::kRecHdr + 8; }
+
 // ------------------------------------------------------------ ragged batches
 //
 // Workspace (int32): [0, 4) instances per class, [4, 8) queue heads, then one
@@ -148,7 +153,7 @@ mp_status_t mp_set_knob(int32_t knob, int32_t value)
         g_mfma_min.store(value);
         return MP_OK;
     case MP_KNOB_SMALL_LIMIT:
-        if (value < 0 || value > 256) return MP_ERR_ARG;
+        if (value < 0 || value > mp::kHeadMaxLimit) return MP_ERR_ARG;
         g_small_limit.store(value);
         return MP_OK;
     }
@@ -215,10 +220,12 @@ mp_status_t mp_shinv_batch(const uint32_t *v, int32_t nv, int32_t h, uint32_t *w
     const size_t bytes = (size_t)words * 4;
     hipStream_t st = (hipStream_t)stream;
     const mp::Knobs kn = knobs();
+    const int head = use_head(kn, nw);
+    if (head && mp::launch_head_shinv(st, v, nv, h, w, nw, batch, kn) != hipSuccess) return MP_ERR_LAUNCH;
     switch (T) {
-    case 256: return status_of(mp::launch_shinv<256>(batch, bytes, st, v, nv, h, w, nw, inst_status, kn));
-    case 512: return status_of(mp::launch_shinv<512>(batch, bytes, st, v, nv, h, w, nw, inst_status, kn));
-    default: return status_of(mp::launch_shinv<1024>(batch, bytes, st, v, nv, h, w, nw, inst_status, kn));
+    case 256: return status_of(mp::launch_shinv<256>(batch, bytes, st, v, nv, h, w, nw, inst_status, kn, head));
+    case 512: return status_of(mp::launch_shinv<512>(batch, bytes, st, v, nv, h, w, nw, inst_status, kn, head));
+    default: return status_of(mp::launch_shinv<1024>(batch, bytes, st, v, nv, h, w, nw, inst_status, kn, head));
     }
 }
 
@@ -236,10 +243,15 @@ mp_status_t mp_divrem_batch(const uint32_t *u, int32_t nu, const uint32_t *v, in
     const size_t bytes = (size_t)words * 4;
     hipStream_t st = (hipStream_t)stream;
     const mp::Knobs kn = knobs();
+    const int head = use_head(kn, nq);
+    if (head && mp::launch_head_divrem(st, u, nu, v, nv, q, nq, batch, kn) != hipSuccess) return MP_ERR_LAUNCH;
     switch (T) {
-    case 256: return status_of(mp::launch_divrem<256>(batch, bytes, st, u, nu, v, nv, q, nq, r, inst_status, kn));
-    case 512: return status_of(mp::launch_divrem<512>(batch, bytes, st, u, nu, v, nv, q, nq, r, inst_status, kn));
-    default: return status_of(mp::launch_divrem<1024>(batch, bytes, st, u, nu, v, nv, q, nq, r, inst_status, kn));
+    case 256:
+        return status_of(mp::launch_divrem<256>(batch, bytes, st, u, nu, v, nv, q, nq, r, inst_status, kn, head));
+    case 512:
+        return status_of(mp::launch_divrem<512>(batch, bytes, st, u, nu, v, nv, q, nq, r, inst_status, kn, head));
+    default:
+        return status_of(mp::launch_divrem<1024>(batch, bytes, st, u, nu, v, nv, q, nq, r, inst_status, kn, head));
     }
 }
 
@@ -289,10 +301,14 @@ mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint
     }
     hipStream_t st = (hipStream_t)stream;
     int32_t *ws = (int32_t *)workspace;
+    const mp::Knobs kn = knobs();
     hipLaunchKernelGGL(k_ragged_prep, dim3(1), dim3(1024), 0, st, desc, count, u_limbs, v_limbs, q_limbs,
                        r_limbs, inst_status, ws);
-    if (hipGetLastError() != hipSuccess || hipEventRecord(ev_fork[dev], st) != hipSuccess) return MP_ERR_LAUNCH;
-    const mp::Knobs kn = knobs();
+    if (hipGetLastError() != hipSuccess) return MP_ERR_LAUNCH;
+    const int head = kn.small_limit > 0;
+    if (head && mp::launch_head_ragged(st, u_pool, v_pool, desc, q_pool, ws, count, kn) != hipSuccess)
+        return MP_ERR_LAUNCH;
+    if (hipEventRecord(ev_fork[dev], st) != hipSuccess) return MP_ERR_LAUNCH;
     for (int c = 0; c < kClasses; c++) {
         hipStream_t fs = fork[dev][c];
         if (hipStreamWaitEvent(fs, ev_fork[dev], 0) != hipSuccess) return MP_ERR_LAUNCH;
@@ -308,9 +324,18 @@ mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint
         const int grid = cus[dev] * wpc;
         hipError_t e;
         switch (T) {
-        case 256: e = mp::launch_ragged<256>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c, count, kn); break;
-        case 512: e = mp::launch_ragged<512>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c, count, kn); break;
-        default: e = mp::launch_ragged<1024>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c, count, kn); break;
+        case 256:
+            e = mp::launch_ragged<256>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c,
+                                       count, kn, head);
+            break;
+        case 512:
+            e = mp::launch_ragged<512>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c,
+                                       count, kn, head);
+            break;
+        default:
+            e = mp::launch_ragged<1024>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c,
+                                        count, kn, head);
+            break;
         }
         if (e != hipSuccess || hipEventRecord(ev_join[dev][c], fs) != hipSuccess ||
             hipStreamWaitEvent(st, ev_join[dev][c], 0) != hipSuccess)

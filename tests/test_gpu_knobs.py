@@ -1,0 +1,106 @@
+"""Every launch configuration gives the oracle's bits.
+
+The run-time knobs choose where the work runs (the head launch for the
+early Refine iterations, or the per-instance workgroups for all of them;
+products on the matrix cores or on the vector ALU), never what is computed:
+each setting is compared element by element with the oracle on structured
+divisors and on samples of the named workloads, through the C ABI."""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_06386_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+B = 1 << 32
+
+# (small_limit, mfma_min): default, no head, short and long head iterations,
+# products on the vector ALU only, matrix cores from 16-limb operands
+SETTINGS = [(64, 64), (0, 64), (16, 64), (128, 64), (64, 1 << 20), (128, 16)]
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2606_06386_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture
+def knobs(mp):
+    old = (mp.get_knob(mp.MP_KNOB_SMALL_LIMIT), mp.get_knob(mp.MP_KNOB_MFMA_MIN))
+
+    def set_(small, mfma):
+        mp.set_knob(mp.MP_KNOB_SMALL_LIMIT, small)
+        mp.set_knob(mp.MP_KNOB_MFMA_MIN, mfma)
+    yield set_
+    set_(*old)
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def _check(mp, u, v, nq, label):
+    import torch
+    q, r, st = mp.divrem(_dev(u), _dev(v), nq=nq)
+    torch.cuda.synchronize()
+    q, r, st = q.cpu().numpy().view(np.uint32), r.cpu().numpy().view(np.uint32), st.cpu().numpy()
+    qo, ro, so = oracle.divrem(u, v, nq=nq, nr=v.shape[1])
+    bad = [j for j in range(len(u)) if st[j] != so[j] or (q[j] != qo[j]).any() or (r[j] != ro[j]).any()]
+    assert not bad, f"{label}: {len(bad)} mismatching instances, first {bad[:8]}"
+
+
+def _structured(width):
+    rng = random.Random(17)
+    rnd = lambda n: rng.getrandbits(32 * n) | (1 << (32 * n - 1))
+    vals = []
+    for k in (1, 2, 5, 11, 19, 40, 70, 130, 300):
+        if k + 2 > width:
+            continue
+        h = min(width, 2 * k + 30 + k // 2)
+        for v in (B ** k + 1, 2 * B ** k + 1, B ** (k + 1) - 1, B ** k + B ** (k - 1), B ** k * 0x80000000 + 1,
+                  B ** k + rnd(k)):
+            for u in (B ** h - 1, v * rnd(max(1, h - k - 1)) + v - 1, rnd(h)):
+                if u.bit_length() <= 32 * width:
+                    vals.append((u, v))
+    return (np.stack([I.from_int(a, width) for a, _ in vals]), np.stack([I.from_int(b, width) for _, b in vals]))
+
+
+@pytest.mark.parametrize("small,mfma", SETTINGS)
+def test_structured_every_setting(mp, knobs, small, mfma):
+    knobs(small, mfma)
+    u, v = _structured(512)
+    _check(mp, u, v, 512, f"structured small={small} mfma={mfma}")
+    # a quotient row too short for a head record: the per-instance workgroups do every step
+    _check(mp, u[:, :40], np.where(np.arange(512)[None, :] < 40, v, 0)[:, :40], 12, "narrow q")
+
+
+@pytest.mark.parametrize("small,mfma", SETTINGS)
+def test_workload_samples_every_setting(mp, knobs, small, mfma):
+    knobs(small, mfma)
+    c = I.config_c2(index=np.arange(0, 4096, 16))       # 256 instances, all five adversarial families
+    _check(mp, c["u"], c["v"], c["nq"], f"2^16 sample small={small} mfma={mfma}")
+    c = I.config_c3(index=np.arange(0, 256, 32))        # 8 instances at 2^18 bits
+    _check(mp, c["u"], c["v"], c["nq"], f"2^18 sample small={small} mfma={mfma}")
+
+
+@pytest.mark.parametrize("small", [0, 64, 128])
+def test_shinv_every_head_setting(mp, knobs, small):
+    import torch
+    knobs(small, 64)
+    vals = []
+    for k in (1, 3, 10, 33, 64, 100, 200):
+        vals += [B ** k + 1, 2 * B ** k + 1, B ** (k + 1) - 1, B ** k + B ** (k - 1), B ** k + 12345]
+    v = np.stack([I.from_int(x, 202) for x in vals])
+    for h in (40, 150, 400):
+        w, st = mp.shinv(_dev(v), h, nw=h + 1)
+        torch.cuda.synchronize()
+        wo, so = oracle.shinv(v, h, nw=h + 1)
+        assert (st.cpu().numpy() == so).all()
+        assert (w.cpu().numpy().view(np.uint32) == wo).all(), f"shinv h={h} small={small}"

@@ -172,6 +172,28 @@ def test_divrem_2p18_full_batch(mp):
     _expect_divrem(mp, c["u"], c["v"], c["nq"], c["name"])
 
 
+def test_divrem_2p17_direct(mp):
+    """Dividends of 4096 limbs (the 512-thread workgroup) against the oracle
+    directly: random divisors of 1024..4096 limbs and the B^k + 1, 2B^k + 1
+    families."""
+    rng = random.Random(4096)
+    n = 4096
+    us, vs = [], []
+    for i in range(48):
+        k = rng.randint(1024, 4096)
+        us.append(_rnd(rng, n))
+        vs.append(_rnd(rng, k))
+    for k in (1023, 1500, 2047, 3000, 4094):
+        for v in (B ** k + 1, 2 * B ** k + 1):
+            us.append(B ** n - 1)
+            vs.append(v)
+    for k in (1100, 2048, 3500):
+        v = _rnd(rng, k)
+        us.append(v * _rnd(rng, n - k) + v - 1)
+        vs.append(v)
+    _expect_divrem(mp, _stack(us, n), _stack(vs, n), n, "2^17 direct")
+
+
 def test_divrem_2p18_structured(mp):
     """Full-depth Newton schedules at 2^18 bits with structured divisors."""
     n = 8192
