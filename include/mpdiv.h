@@ -46,7 +46,8 @@ typedef enum {
     MP_ERR_ARG = 1,     /* null pointer, non-positive width, negative batch */
     MP_ERR_SIZE = 2,    /* an operand width exceeds mp_max_limbs() */
     MP_ERR_LAUNCH = 3,  /* the HIP launch failed */
-    MP_ERR_DEVICE = 4   /* no usable gfx950 device */
+    MP_ERR_DEVICE = 4,  /* no usable gfx950 device */
+    MP_ERR_COUNT = 5    /* mp_divrem_ragged_static: count > MP_STATIC_MAX_COUNT */
 } mp_status_t;
 
 enum { MP_INST_OK = 0, MP_INST_DIVZERO = 1, MP_INST_QWIDTH = 2, MP_INST_INTERNAL = 3, MP_INST_BADDESC = 4 };
@@ -120,6 +121,25 @@ mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint
 
 /* bytes of workspace mp_divrem_ragged needs for count instances */
 int64_t mp_ragged_workspace_bytes(int32_t count);
+
+/*
+ * mp_divrem_ragged without a workspace argument and without any allocation,
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and per-instance status as mp_divrem_ragged.  The
+ * work queue lives in a static array of the library, one per GPU (1 MiB,
+ * held until the process ends), so count must not exceed
+ * MP_STATIC_MAX_COUNT (else MP_ERR_COUNT, nothing launched).  The call
+ * allocates nothing and creates no stream or event: all its kernels run on
+ * `stream`, one after another.  Every call on a GPU shares that GPU's array:
+ * calls that may overlap on one GPU (different streams, concurrent graph
+ * replays) race and must be serialised by the caller.
+ */
+#define MP_STATIC_MAX_COUNT 65536
+mp_status_t mp_divrem_ragged_static(const uint32_t *u_pool, int64_t u_limbs, const uint32_t *v_pool,
+                                    int64_t v_limbs, const mp_desc_t *desc, uint32_t *q_pool, int64_t q_limbs,
+                                    uint32_t *r_pool, int64_t r_limbs, int32_t *inst_status, int32_t count,
+                                    void *stream);
 
 /*
  * Launch configuration of width class cls (0..3) for mp_divrem_ragged:

@@ -13,11 +13,13 @@ import torch
 
 from . import build as _build
 
-MP_OK, MP_ERR_ARG, MP_ERR_SIZE, MP_ERR_LAUNCH, MP_ERR_DEVICE = range(5)
+MP_OK, MP_ERR_ARG, MP_ERR_SIZE, MP_ERR_LAUNCH, MP_ERR_DEVICE, MP_ERR_COUNT = range(6)
+MP_STATIC_MAX_COUNT = 65536
 MP_INST_OK, MP_INST_DIVZERO, MP_INST_QWIDTH, MP_INST_INTERNAL, MP_INST_BADDESC = range(5)
 
 # every entry point declared in include/mpdiv.h
-EXPORTS = ("mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_divrem_ragged", "mp_ragged_workspace_bytes",
+EXPORTS = ("mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_divrem_ragged", "mp_divrem_ragged_static",
+           "mp_ragged_workspace_bytes",
            "mp_ragged_config", "mp_set_knob", "mp_get_knob", "mp_lds_bytes", "mp_status_str", "mp_max_limbs")
 MP_KNOB_MFMA_MIN, MP_KNOB_SMALL_LIMIT = 0, 1
 MP_OP_MUL, MP_OP_DIVREM, MP_OP_SHINV = 0, 1, 2
@@ -46,6 +48,8 @@ def lib():
         _i64 = ctypes.c_int64
         L.mp_divrem_ragged.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _i32, _vp, _vp]
         L.mp_divrem_ragged.restype = _i32
+        L.mp_divrem_ragged_static.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _i32, _vp]
+        L.mp_divrem_ragged_static.restype = _i32
         L.mp_ragged_workspace_bytes.argtypes = [_i32]
         L.mp_ragged_workspace_bytes.restype = _i64
         L.mp_ragged_config.argtypes = [_i32, _i32, _i32]
@@ -153,6 +157,13 @@ class Ragged:
                                       self.desc.data_ptr(), self.q.data_ptr(), self.q.numel(), self.r.data_ptr(),
                                       self.r.numel(), self.status.data_ptr(), self.count, self.ws.data_ptr(),
                                       _stream(stream)), "mp_divrem_ragged")
+
+    def run_static(self, stream=None):
+        """The same batch through mp_divrem_ragged_static (no workspace)."""
+        _raise(lib().mp_divrem_ragged_static(self.u.data_ptr(), self.u.numel(), self.v.data_ptr(), self.v.numel(),
+                                             self.desc.data_ptr(), self.q.data_ptr(), self.q.numel(),
+                                             self.r.data_ptr(), self.r.numel(), self.status.data_ptr(), self.count,
+                                             _stream(stream)), "mp_divrem_ragged_static")
 
 
 def set_knob(knob, value):

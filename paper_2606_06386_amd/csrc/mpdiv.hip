@@ -127,6 +127,104 @@ namespace {
 
 mp_status_t status_of(hipError_t e) { return e == hipSuccess ? MP_OK : MP_ERR_LAUNCH; }
 
+// compute units of the current device (queried once per device)
+int device_cus()
+{
+    static int cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cus[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+        cus[dev] = prop.multiProcessorCount;
+    }
+    return cus[dev];
+}
+
+// The work queue of mp_divrem_ragged_static: a library-owned array of one
+// ragged workspace for MP_STATIC_MAX_COUNT instances (1 MiB), one copy per
+// GPU, kept until the process ends.  Host code never uses the array's name as
+// an address: static_scratch() returns this device's copy's address, fetched
+// once per device with that device current.
+static __device__ __align__(256) int32_t scratch[kWsHeader + kClasses * MP_STATIC_MAX_COUNT];
+
+int32_t *static_scratch()
+{
+    static void *ptr[64];
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        ptr[dev] = p;
+    }
+    return (int32_t *)ptr[dev];
+}
+
+// fork streams and events of the concurrent class kernels
+struct Forks {
+    hipStream_t fs[kClasses];
+    hipEvent_t ev_fork, ev_join[kClasses];
+};
+
+// The launches of one ragged batch: descriptor check and bucketing, heads,
+// then one persistent kernel per width class, each on its own fork stream
+// joined back into st (all on st, one after another, when fk is null).  The
+// preparation kernel sets every counter of the workspace, so it needs no
+// clearing.  Called with g_ragged_mu held.
+mp_status_t ragged_launch(const uint32_t *u_pool, int64_t u_limbs, const uint32_t *v_pool, int64_t v_limbs,
+                          const mp_desc_t *desc, uint32_t *q_pool, int64_t q_limbs, uint32_t *r_pool,
+                          int64_t r_limbs, int32_t *inst_status, int32_t count, int32_t *ws, hipStream_t st,
+                          const Forks *fk)
+{
+    const int cus = device_cus();
+    if (cus <= 0) return MP_ERR_DEVICE;
+    const mp::Knobs kn = knobs();
+    hipLaunchKernelGGL(k_ragged_prep, dim3(1), dim3(1024), 0, st, desc, count, u_limbs, v_limbs, q_limbs,
+                       r_limbs, inst_status, ws);
+    if (hipGetLastError() != hipSuccess) return MP_ERR_LAUNCH;
+    const int head = kn.small_limit > 0;
+    if (head && mp::launch_head_ragged(st, u_pool, v_pool, desc, q_pool, ws, count, kn) != hipSuccess)
+        return MP_ERR_LAUNCH;
+    if (fk && hipEventRecord(fk->ev_fork, st) != hipSuccess) return MP_ERR_LAUNCH;
+    for (int c = 0; c < kClasses; c++) {
+        hipStream_t fs = fk ? fk->fs[c] : st;
+        if (fk && hipStreamWaitEvent(fs, fk->ev_fork, 0) != hipSuccess) return MP_ERR_LAUNCH;
+        const int T = g_ragged.threads[c];
+        // LDS of the class's widest instance (a scan over every divisor length: computed once)
+        static size_t lds_bytes[kClasses][3];
+        const int ti = T == 256 ? 0 : T == 512 ? 1 : 2;
+        if (lds_bytes[c][ti] == 0) lds_bytes[c][ti] = (size_t)mp::div_lds_words(kClassWidth[c], kClassWidth[c], T) * 4;
+        const size_t bytes = lds_bytes[c][ti];
+        if (bytes > (size_t)kLdsWords * 4) return MP_ERR_SIZE;
+        const int fit = (int)(((size_t)kLdsWords * 4) / bytes);
+        const int wpc = g_ragged.wgs_per_cu[c] < fit ? g_ragged.wgs_per_cu[c] : fit;
+        const int grid = cus * wpc;
+        hipError_t e;
+        switch (T) {
+        case 256:
+            e = mp::launch_ragged<256>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c,
+                                       count, kn, head);
+            break;
+        case 512:
+            e = mp::launch_ragged<512>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c,
+                                       count, kn, head);
+            break;
+        default:
+            e = mp::launch_ragged<1024>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c,
+                                        count, kn, head);
+            break;
+        }
+        if (e != hipSuccess) return MP_ERR_LAUNCH;
+        if (fk && (hipEventRecord(fk->ev_join[c], fs) != hipSuccess ||
+                   hipStreamWaitEvent(st, fk->ev_join[c], 0) != hipSuccess))
+            return MP_ERR_LAUNCH;
+    }
+    return MP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -139,6 +237,7 @@ const char *mp_status_str(mp_status_t s)
     case MP_ERR_SIZE: return "MP_ERR_SIZE: operand wider than mp_max_limbs()";
     case MP_ERR_LAUNCH: return "MP_ERR_LAUNCH: kernel launch failed";
     case MP_ERR_DEVICE: return "MP_ERR_DEVICE: no usable gfx950 device";
+    case MP_ERR_COUNT: return "MP_ERR_COUNT: count exceeds MP_STATIC_MAX_COUNT (the static work queue's size)";
     }
     return "unknown mp_status_t";
 }
@@ -285,63 +384,36 @@ mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MP_ERR_DEVICE;
     // per-device fork streams and events (default priority), made once
-    static hipStream_t fork[64][kClasses];
-    static hipEvent_t ev_fork[64], ev_join[64][kClasses];
-    static int cus[64];
-    if (cus[dev] == 0) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MP_ERR_DEVICE;
+    static Forks forks[64];
+    static bool made[64];
+    if (!made[dev]) {
         for (int c = 0; c < kClasses; c++) {
-            if (hipStreamCreateWithFlags(&fork[dev][c], hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&ev_join[dev][c], hipEventDisableTiming) != hipSuccess)
+            if (hipStreamCreateWithFlags(&forks[dev].fs[c], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&forks[dev].ev_join[c], hipEventDisableTiming) != hipSuccess)
                 return MP_ERR_LAUNCH;
         }
-        if (hipEventCreateWithFlags(&ev_fork[dev], hipEventDisableTiming) != hipSuccess) return MP_ERR_LAUNCH;
-        cus[dev] = prop.multiProcessorCount;
+        if (hipEventCreateWithFlags(&forks[dev].ev_fork, hipEventDisableTiming) != hipSuccess) return MP_ERR_LAUNCH;
+        made[dev] = true;
     }
-    hipStream_t st = (hipStream_t)stream;
-    int32_t *ws = (int32_t *)workspace;
-    const mp::Knobs kn = knobs();
-    hipLaunchKernelGGL(k_ragged_prep, dim3(1), dim3(1024), 0, st, desc, count, u_limbs, v_limbs, q_limbs,
-                       r_limbs, inst_status, ws);
-    if (hipGetLastError() != hipSuccess) return MP_ERR_LAUNCH;
-    const int head = kn.small_limit > 0;
-    if (head && mp::launch_head_ragged(st, u_pool, v_pool, desc, q_pool, ws, count, kn) != hipSuccess)
-        return MP_ERR_LAUNCH;
-    if (hipEventRecord(ev_fork[dev], st) != hipSuccess) return MP_ERR_LAUNCH;
-    for (int c = 0; c < kClasses; c++) {
-        hipStream_t fs = fork[dev][c];
-        if (hipStreamWaitEvent(fs, ev_fork[dev], 0) != hipSuccess) return MP_ERR_LAUNCH;
-        const int T = g_ragged.threads[c];
-        // LDS of the class's widest instance (a scan over every divisor length: computed once)
-        static size_t lds_bytes[kClasses][3];
-        const int ti = T == 256 ? 0 : T == 512 ? 1 : 2;
-        if (lds_bytes[c][ti] == 0) lds_bytes[c][ti] = (size_t)mp::div_lds_words(kClassWidth[c], kClassWidth[c], T) * 4;
-        const size_t bytes = lds_bytes[c][ti];
-        if (bytes > (size_t)kLdsWords * 4) return MP_ERR_SIZE;
-        const int fit = (int)(((size_t)kLdsWords * 4) / bytes);
-        const int wpc = g_ragged.wgs_per_cu[c] < fit ? g_ragged.wgs_per_cu[c] : fit;
-        const int grid = cus[dev] * wpc;
-        hipError_t e;
-        switch (T) {
-        case 256:
-            e = mp::launch_ragged<256>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c,
-                                       count, kn, head);
-            break;
-        case 512:
-            e = mp::launch_ragged<512>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c,
-                                       count, kn, head);
-            break;
-        default:
-            e = mp::launch_ragged<1024>(grid, bytes, fs, u_pool, v_pool, desc, q_pool, r_pool, inst_status, ws, c,
-                                        count, kn, head);
-            break;
-        }
-        if (e != hipSuccess || hipEventRecord(ev_join[dev][c], fs) != hipSuccess ||
-            hipStreamWaitEvent(st, ev_join[dev][c], 0) != hipSuccess)
-            return MP_ERR_LAUNCH;
-    }
-    return MP_OK;
+    return ragged_launch(u_pool, u_limbs, v_pool, v_limbs, desc, q_pool, q_limbs, r_pool, r_limbs, inst_status,
+                         count, (int32_t *)workspace, (hipStream_t)stream, &forks[dev]);
+}
+
+mp_status_t mp_divrem_ragged_static(const uint32_t *u_pool, int64_t u_limbs, const uint32_t *v_pool,
+                                    int64_t v_limbs, const mp_desc_t *desc, uint32_t *q_pool, int64_t q_limbs,
+                                    uint32_t *r_pool, int64_t r_limbs, int32_t *inst_status, int32_t count,
+                                    void *stream)
+{
+    if (!u_pool || !v_pool || !desc || !q_pool || !r_pool || !inst_status || count < 0) return MP_ERR_ARG;
+    if (u_limbs < 0 || v_limbs < 0 || q_limbs < 0 || r_limbs < 0) return MP_ERR_ARG;
+    if (count > MP_STATIC_MAX_COUNT) return MP_ERR_COUNT;
+    if (count == 0) return MP_OK;
+    if (!device_ok()) return MP_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_ragged_mu);
+    int32_t *ws = static_scratch();
+    if (!ws) return MP_ERR_DEVICE;
+    return ragged_launch(u_pool, u_limbs, v_pool, v_limbs, desc, q_pool, q_limbs, r_pool, r_limbs, inst_status,
+                         count, ws, (hipStream_t)stream, nullptr);
 }
 
 }  // extern "C"

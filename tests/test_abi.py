@@ -26,6 +26,7 @@ def L():
 def test_exports_every_declared_symbol(L):
     names = _declared()
     assert set(names) == {"mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_divrem_ragged",
+                          "mp_divrem_ragged_static",
                           "mp_ragged_workspace_bytes", "mp_ragged_config", "mp_set_knob", "mp_get_knob",
                           "mp_lds_bytes", "mp_status_str", "mp_max_limbs"}
     for n in names:
@@ -36,7 +37,7 @@ def test_exports_every_declared_symbol(L):
 
 def test_limits_and_status_strings(L):
     assert L.mp_max_limbs() == 8192
-    for code in range(5):
+    for code in range(6):
         assert L.mp_status_str(code).decode().startswith("MP_")
 
 
@@ -61,6 +62,14 @@ def test_host_argument_errors(L):
     assert L.mp_divrem_ragged(p, 4, p, 4, p, p, 4, p, 4, p, 1, None, None) == MP_ERR_ARG
     assert L.mp_divrem_ragged(p, 4, p, 4, p, p, 4, p, 4, p, -1, p, None) == MP_ERR_ARG
     assert L.mp_divrem_ragged(p, 4, p, 4, p, p, 4, p, 4, p, 0, p, None) == MP_OK
+    # the no-allocation variant: same checks, and count beyond its static work queue
+    from paper_2606_06386_amd.binding import MP_ERR_COUNT, MP_STATIC_MAX_COUNT
+    assert L.mp_divrem_ragged_static(None, 4, p, 4, p, p, 4, p, 4, p, 1, None) == MP_ERR_ARG
+    assert L.mp_divrem_ragged_static(p, 4, p, 4, p, p, 4, p, 4, None, 1, None) == MP_ERR_ARG
+    assert L.mp_divrem_ragged_static(p, 4, p, 4, p, p, 4, p, 4, p, -1, None) == MP_ERR_ARG
+    assert L.mp_divrem_ragged_static(p, 4, p, 4, p, p, 4, p, 4, p, MP_STATIC_MAX_COUNT + 1, None) == MP_ERR_COUNT
+    assert L.mp_divrem_ragged_static(p, 4, p, 4, p, p, 4, p, 4, p, 0, None) == MP_OK
+    assert L.mp_ragged_workspace_bytes(MP_STATIC_MAX_COUNT) == 4 * (16 + 4 * MP_STATIC_MAX_COUNT)
     assert L.mp_ragged_workspace_bytes(0) > 0
     assert L.mp_ragged_workspace_bytes(1000) >= 4 * 1000 * 4
     assert L.mp_ragged_config(4, 256, 1) == MP_ERR_ARG
