@@ -267,11 +267,35 @@ def phase_trace(args):
         prev = np.where(col > 0, col, prev)
         last = prev
     res["u_times_s"] = float(np.mean(rows[:, 5] - last))
+    # the head launch (one wave per instance): its own stamps
+    L.mp_trace_read_head.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.mp_trace_read_head.restype = ctypes.c_int
+    hs = np.zeros((batch, 32), dtype=np.uint64)
+    assert L.mp_trace_read_head(hs.ctypes.data, batch) == 0
+    hs = hs.astype(np.float64)
+    hfull = (hs[:, [0, 1, 2, 3, 4]] > 0).all(axis=1)
+    hr = hs[hfull]
+    head = {"instances": int(hfull.sum())}
+    if len(hr):
+        head["precisions"] = float(np.mean(hr[:, 1] - hr[:, 0]))
+        head["stage_v"] = float(np.mean(hr[:, 2] - hr[:, 1]))
+        head["initial_approx"] = float(np.mean(hr[:, 3] - hr[:, 2]))
+        prev_h = hr[:, 3].copy()
+        for i in range(16):
+            col = hr[:, 16 + i]
+            if not (col > 0).any():
+                continue
+            head["iter_%d" % i] = float(np.mean(np.where(col > 0, col - prev_h, 0)))
+            prev_h = np.where(col > 0, col, prev_h)
+        head["record"] = float(np.mean(hr[:, 4] - prev_h))
+        head["total"] = float(np.mean(hr[:, 4] - hr[:, 0]))
+        head["span_all_waves"] = float(hr[:, 4].max() - hr[:, 0].min())
     res["v_times_q"] = float(np.mean(rows[:, 6] - rows[:, 5]))
     res["corrections"] = float(np.mean(rows[:, 7] - rows[:, 6]))
     res["store"] = float(np.mean(rows[:, 8] - rows[:, 7]))
     total = float(np.mean(rows[:, 8] - rows[:, 0]))
-    print(json.dumps({"phase_trace": c["name"], "kernel": "k_divrem<256>", "instances": int(full.sum()),
+    print(json.dumps({"phase_trace": c["name"], "kernel": "k_divrem<256>", "head": head,
+                      "instances": int(full.sum()),
                       "knobs": knobs_now(), "clock": "shader cycles (s_memtime) of workgroup thread 0",
                       "total_cycles": total, "cycles": res,
                       "share": {k: v / total for k, v in res.items()}}), flush=True)

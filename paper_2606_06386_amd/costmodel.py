@@ -55,7 +55,7 @@ def refine_cost(h: int, k: int, clipped: bool = False) -> int:
         L = nvp + nw - (l - g) + 1
         total += nvp * nw if L >= hp else low_product_cost(nvp, nw, L)
         sh = k + l + m - s + g - 2 * m         # Step: w * x, x ~ prec(v') limbs
-        cs = (max(sh - 2, 0) & ~7) if clipped and nw + nvp >= sh + 2 else 0
+        cs = (max(sh - 2, 0) & ~7) if clipped and nw + nvp >= sh + 1 else 0
         total += high_product_cost(nw, nvp, cs)
         if i >= 2:
             l = l + m - 1

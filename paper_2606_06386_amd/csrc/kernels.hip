@@ -22,10 +22,15 @@
 
 namespace mp {
 
-// Division kernels ask the compiler for at most 128 registers per lane, so
-// that four waves share each SIMD: four 256-thread workgroups per compute
-// unit at 2^16 bits, where the LDS plan also allows four.
-#define MP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4, 8)))
+// Division kernels ask the compiler for at most 128 registers per lane (four
+// waves per SIMD: four 256-thread workgroups per compute unit at 2^16 bits).
+// MP_BODY_WAVES=5 builds the 256-thread kernels for five (96 registers, a few
+// spills; the LDS plan at 2^16 bits also allows five): measured slower, as the
+// instances then contend for the same units.
+#ifndef MP_BODY_WAVES
+#define MP_BODY_WAVES 4
+#endif
+#define MP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(T == 256 ? MP_BODY_WAVES : 4, 8)))
 
 // Workspace of a ragged batch (int32): [0, 4) instances per class, [4, 8)
 // queue heads, then one list of instance indices per class, each `count` long.
@@ -238,6 +243,15 @@ template hipError_t launch_ragged<MP_KT>(int, size_t, hipStream_t, const uint32_
 #endif
 
 }  // namespace mp
+
+#if defined(MP_PHASE_TRACE) && MP_KFAMILY == 4
+// copies the head stamps of the first `waves` instances (32 per instance) to host memory
+extern "C" int mp_trace_read_head(uint64_t *dst, int waves)
+{
+    return (int)hipMemcpyFromSymbol(dst, HIP_SYMBOL(mp_trace_buf), (size_t)waves * 32 * sizeof(uint64_t), 0,
+                                    hipMemcpyDeviceToHost);
+}
+#endif
 
 #if defined(MP_PHASE_TRACE) && MP_KFAMILY == 2 && MP_KT == 256
 // copies the stamps of the first `blocks` workgroups (32 per workgroup) to host memory

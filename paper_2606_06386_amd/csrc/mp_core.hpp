@@ -32,6 +32,7 @@ constexpr int kHeadMaxLimbs = 9 * kLanes;   // longest operand of a one-wave add
 
 // control block at the start of the instance's LDS (32-bit words)
 constexpr int kCtlRed = 0;       // 3 x 16 per-wave reduction slots
+constexpr int kCtlSticky = 32;   // 16 per-wave sticky flags of an addsub (the third reduction row)
 constexpr int kCtlScan = 48;     // 16 x (generate, propagate) wave summaries
 constexpr int kCtlPrec = 80;     // 16 per-wave result-precision slots of the last addsub
 constexpr int kCtlStrip = 96;    // 2 words per strip carry, up to 72 strips
@@ -85,15 +86,16 @@ struct PowB {
 };
 
 // strip carries of a product: carry e_s (64-bit) enters at column
-// (s+1)*kStrip - off
+// (s+1)*width - off
 struct StripCarries {
     const uint32_t *sc;
     int nstrips;
     int off;
+    int width;
     MP_DEV uint32_t operator()(int k) const
     {
         const int kk = k + off;
-        int s = (kk / kStrip) - 1, o = kk % kStrip;
+        int s = (kk / width) - 1, o = kk % width;
         if (s < 0 || s >= nstrips || o > 1) return 0u;
         return sc[2 * s + o];
     }
@@ -117,14 +119,21 @@ struct Discard {
 
 // ------------------------------------------------------------- reductions
 
+MP_DEV uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+
+// maximum of x over the wave (the same value on every lane): pairs, quads,
+// half rows and rows by DPP permutations, then row 1 and 3 take the row below
+// (row_bcast:15) and rows 2 and 3 take lane 31 (row_bcast:31), so lane 63
+// holds the maximum of all 64 lanes
 MP_DEV uint32_t wave_max(uint32_t x)
 {
-#pragma unroll
-    for (int m = 1; m < kLanes; m <<= 1) {
-        uint32_t y = shfl_xor(x, m);
-        x = x > y ? x : y;
-    }
-    return x;
+    x = umax(x, dpp<kDppQuadSwap1>(x));
+    x = umax(x, dpp<kDppQuadSwap2>(x));
+    x = umax(x, dpp<kDppRowHalfMirror>(x));
+    x = umax(x, dpp<kDppRowMirror>(x));
+    x = umax(x, dpp<kDppRowBcast15, 0xA>(x));
+    x = umax(x, dpp<kDppRowBcast31, 0xC>(x));
+    return readlane(x, kLanes - 1);
 }
 
 // maximum of one value per thread over the workgroup (same on every thread)
@@ -168,8 +177,6 @@ MP_DEV void wg_max_n(uint32_t *ctl, uint32_t (&x)[N])
         x[i] = uniform(r);
     }
 }
-
-MP_DEV uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
 // max over k in [0, n) of f(k)  (f(k) >= 0).  Four independent reads per
 // step, so their latencies overlap.
@@ -220,9 +227,9 @@ MP_DEV int cmp(uint32_t *ctl, int n, const FX &x, const FY &y)
 // the internal barrier and outputs written after it, so out may overwrite
 // the storage x or y read from.  The precision of z (1 + index of its top
 // nonzero limb, 0 for zero) is left in per-wave slots for read_prec.
-template <int T, int CM, class FX, class FY, class FO>
+template <int T, int CM, class FX, class FY, class FO, class FS>
 MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin,
-                             const FX &x, const FY &y, const FO &out)
+                             const FX &x, const FY &y, const FO &out, const FS &stk)
 {
     constexpr int W = T / kLanes;
     constexpr bool kPre = CM <= 9;   // short chunks: all reads first, so their latencies overlap
@@ -231,6 +238,7 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
     uint32_t z[CM], av[CP], bv[CP];
     uint32_t c = 0;
     bool prop = true;
+    const bool sk = stk.any(tid<T>());   // this thread's part of the sticky carry-in
     if (kPre) {
 #pragma unroll
         for (int j = 0; j < CP; j++) {
@@ -261,16 +269,24 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
     const uint64_t G = ballot(c != 0), P = ballot(prop), X = G | P;
     const uint64_t s0 = X + G;
     const int w = uniform(tid<T>() / kLanes);
+    const uint64_t SK = FS::kActive ? ballot(sk) : 0;
     uint32_t cin_w = cin, cout = cin;
     if constexpr (W == 1) {
         // one wave: its own summary is the whole scan
+        if (FS::kActive && SK) cin = cin_w = 1u;
         cout = (s0 < X ? 1u : 0u) | ((~P == 0 ? 1u : 0u) & cin);
     } else {
         if (lane() == 0) {
             ctl[kCtlScan + 2 * w] = s0 < X ? 1u : 0u;      // wave generates
             ctl[kCtlScan + 2 * w + 1] = (~P == 0) ? 1u : 0u;  // wave propagates
+            if (FS::kActive) ctl[kCtlSticky + w] = SK ? 1u : 0u;
         }
         bar<T>();
+        if constexpr (FS::kActive) {
+#pragma unroll
+            for (int v = 0; v < W; v++) cin |= ctl[kCtlSticky + v];
+            cin_w = cout = cin;
+        }
         // scan of the wave summaries: carry into this wave, and out of the number
 #pragma unroll
         for (int v = 0; v < W; v++) {
@@ -321,22 +337,43 @@ MP_DEV int read_prec(uint32_t *ctl, int off = 0)
     return p > 0 ? p : 0;
 }
 
-template <int T, class FX, class FY, class FO>
+// no sticky carry-in
+struct NoSticky {
+    static constexpr bool kActive = false;
+    MP_DEV bool any(int) const { return false; }
+};
+
+// sticky carry-in: 1 when any limb p[j], j in [0, n), is nonzero (the threads
+// each test a strided share before the carry scan)
+template <int T>
+struct StickyAny {
+    static constexpr bool kActive = true;
+    const uint32_t *p;
+    int n;
+    MP_DEV bool any(int t) const
+    {
+        bool r = false;
+        for (int j = t; j < n; j += T) r = r || p[j] != 0u;
+        return r;
+    }
+};
+
+template <int T, class FX, class FY, class FO, class FS = NoSticky>
 MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
-                       const FX &x, const FY &y, const FO &out)
+                       const FX &x, const FY &y, const FO &out, const FS &stk = FS{})
 {
     bar<T>();
     // odd chunk length: lanes then touch LDS with an odd word stride (no bank conflicts)
     const int C = ((n + T - 1) / T) | 1;
-    if (C == 1) return addsub_chunk<T, 1>(ctl, n, C, sub, cin, x, y, out);
-    if (C == 3) return addsub_chunk<T, 3>(ctl, n, C, sub, cin, x, y, out);
-    if (C <= 5) return addsub_chunk<T, 5>(ctl, n, C, sub, cin, x, y, out);
+    if (C == 1) return addsub_chunk<T, 1>(ctl, n, C, sub, cin, x, y, out, stk);
+    if (C == 3) return addsub_chunk<T, 3>(ctl, n, C, sub, cin, x, y, out, stk);
+    if (C <= 5) return addsub_chunk<T, 5>(ctl, n, C, sub, cin, x, y, out, stk);
     // a single wave (a head) handles at most kHeadMaxLimbs limbs per operation
     if constexpr (T == kLanes) {
-        return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out);
+        return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out, stk);
     } else {
-        if (C <= 9) return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out);
-        return addsub_chunk<T, kCMax>(ctl, n, C, sub, cin, x, y, out);
+        if (C <= 9) return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out, stk);
+        return addsub_chunk<T, kCMax>(ctl, n, C, sub, cin, x, y, out, stk);
     }
 }
 
@@ -422,10 +459,11 @@ MP_DEV void strip_resolve(uint32_t *ctl, int s, int K0, const uint64_t (&lo)[4],
 // its carry to column base + (s+1) kStrip), mod B^(ncols - c0); returns the
 // precision as mul's (or -1 without want_prec, saving a barrier)
 template <int T>
-MP_DEV int add_strip_carries(uint32_t *ctl, uint32_t *p, int c0, int ncols, int nstrips, int base, bool want_prec)
+MP_DEV int add_strip_carries(uint32_t *ctl, uint32_t *p, int c0, int ncols, int nstrips, int base, bool want_prec,
+                             int width = kStrip)
 {
     const int n = ncols - c0;
-    addsub<T>(ctl, n, false, 0u, Span{p + c0, 0, n}, StripCarries{ctl + kCtlStrip, nstrips, c0 - base},
+    addsub<T>(ctl, n, false, 0u, Span{p + c0, 0, n}, StripCarries{ctl + kCtlStrip, nstrips, c0 - base, width},
               Store{p + c0, 0, n});
     if (!want_prec) return -1;
     const int e = read_prec<T>(ctl);
@@ -436,9 +474,9 @@ MP_DEV int add_strip_carries(uint32_t *ctl, uint32_t *p, int c0, int ncols, int 
 // ncols short of the full width) ends its top strip at ncols (rounded up to 8
 // limbs) so that the partial strip is the lowest one, which has the fewest
 // products; other products start at c0, leaving the cheap top strip partial.
-MP_DEV int strip_base(int c0, int ncols, int nfull, int nstrips)
+MP_DEV int strip_base(int c0, int ncols, int nfull, int nstrips, int width = kStrip)
 {
-    return (c0 == 0 && ncols < nfull) ? ((ncols + 7) & ~7) - nstrips * kStrip : c0;
+    return (c0 == 0 && ncols < nfull) ? ((ncols + 7) & ~7) - nstrips * width : c0;
 }
 
 // p[c0, ncols) = the columns c0 .. ncols-1 of a * b, ncols <= na + nb (with
@@ -526,6 +564,82 @@ MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
     return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base, want_prec);
 }
 
+// The same product for a single wave, one column per lane: for short
+// operands, where most lanes of a 256-column strip would be idle.  The wave
+// walks strips of 64 columns from the bottom; lane l of strip s sums column
+// K0 + l over the rows in four independent 96-bit accumulators (rows i, i+1,
+// i+2, i+3), reading window limb k - i of each row.  The column sums
+// S_l = s0 + s1 B + s2 B^2 become limbs as t_l = s0_l + s1_(l-1) + s2_(l-2)
+// (neighbour values by DPP lane shifts) plus, in lanes 0 and 1, the carry E
+// of the strip below; then y_l = lo(t_l) + hi(t_(l-1)) has a one-bit carry,
+// resolved by the ballot lookahead.  The carry leaving the strip (into its
+// next two columns) is kept in scalar registers for the next strip, so no
+// pass over the stored limbs follows; the top strip's carry lies above
+// ncols and is dropped.
+template <int T>
+MP_DEV int mul1(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *a, int na, const uint32_t *bw, int nb, int c0,
+                bool want_prec)
+{
+    static_assert(T == kLanes, "mul1 is the single-wave product");
+    (void)ctl;
+    wave_sync();
+    if (na == 0 || nb == 0 || ncols <= c0) {
+        for (int k = c0 + lane(); k < ncols; k += kLanes) p[k] = 0u;
+        return 0;
+    }
+    const int nstrips = (ncols - c0 + kLanes - 1) / kLanes;
+    const int base = strip_base(c0, ncols, na + nb, nstrips, kLanes);
+    const int l = lane();
+    uint64_t E = 0;        // carry into columns K0, K0 + 1 of the current strip
+    int top = 0;           // 1 + highest nonzero stored column
+    for (int s = 0; s < nstrips; s++) {
+        const int K0 = base + s * kLanes, k = K0 + l;
+        const int ilo = imax(0, K0 - nb + 1);
+        const int ihi = imin(na, imin(K0 + kLanes, ncols));
+        uint64_t lo[4] = {0, 0, 0, 0};
+        uint32_t hi[4] = {0, 0, 0, 0};
+        const uint32_t *wp = bw + k;
+        int i = ilo;
+        for (; i + 3 < ihi; i += 4) {
+            const uint32_t w0 = wp[-i], w1 = wp[-i - 1], w2 = wp[-i - 2], w3 = wp[-i - 3];
+            mac4x(lo, hi, a[i], w0, a[i + 1], w1, a[i + 2], w2, a[i + 3], w3);
+        }
+        if (i < ihi) {
+            const uint32_t a1 = i + 1 < ihi ? a[i + 1] : 0u, a2 = i + 2 < ihi ? a[i + 2] : 0u;
+            mac4x(lo, hi, a[i], wp[-i], a1, wp[-i - 1], a2, wp[-i - 2], 0u, 0u);
+        }
+        // the four partial sums of column k, added exactly (each below 2^(64 + 7))
+        uint64_t sl = lo[0];
+        uint32_t sh = hi[0];
+#pragma unroll
+        for (int r = 1; r < 4; r++) {
+            const uint64_t t = sl + lo[r];
+            sh += hi[r] + (t < sl ? 1u : 0u);
+            sl = t;
+        }
+        // limbs: t = s0 + s1 of the lane below + s2 of the lane two below (+ E at the bottom)
+        const uint32_t s1m = shfl_up1((uint32_t)(sl >> 32)), s2m = shfl_up2(sh);
+        const uint32_t e = l == 0 ? (uint32_t)E : l == 1 ? (uint32_t)(E >> 32) : 0u;
+        const uint64_t t = (uint64_t)(uint32_t)sl + s1m + s2m + e;     // < 4 B
+        const uint32_t cm = shfl_up1((uint32_t)(t >> 32));                // 0..3 from the lane below
+        const uint64_t y = (uint64_t)(uint32_t)t + cm;
+        uint32_t z = (uint32_t)y;
+        const bool g = (y >> 32) != 0, pr = z == 0xFFFFFFFFu;
+        const uint64_t G = ballot(g), P = ballot(pr), X = G | P;
+        const uint64_t sum = X + G;
+        z += (uint32_t)(((sum ^ X ^ G) >> l) & 1u);
+        const bool st = k >= c0 && k < ncols;
+        if (st) p[k] = z;
+        const uint64_t nz = ballot(st && z != 0u);
+        if (nz) top = K0 + kLanes - __builtin_clzll(nz);
+        // carry into the next strip: what lanes 62 and 63 pass upward plus the lookahead's carry out
+        const uint32_t s2_62 = readlane(sh, 62), s2_63 = readlane(sh, 63);
+        const uint32_t s1_63 = readlane((uint32_t)(sl >> 32), 63), c_63 = readlane((uint32_t)(t >> 32), 63);
+        E = (uint64_t)s1_63 + s2_62 + c_63 + (sum < X ? 1u : 0u) + ((uint64_t)s2_63 << 32);
+    }
+    return want_prec ? top : -1;
+}
+
 // ---------------------------------------------------- matrix-core product
 //
 // Exact products on the int8 matrix cores.  A number is rewritten in radix 256
@@ -577,13 +691,17 @@ constexpr int kXPad = 16;    // zero words the reversed short operand needs on e
 // kXPad zero words on both sides.  The short operand must not live in xr's
 // padded range unless it is exactly the limbs the conversion reads first
 // (the reads all precede the writes inside addsub).
+//
+// With x_ready the short operand's digits are already in xr (the same number
+// converted by an earlier call) and only the long operand is converted.
 template <int T, class FY, class FX>
 MP_DEV void mfma_operands(uint32_t *ctl, const FY &y, int ny, uint32_t *yb, int yclear,
-                          const FX &x, int nx, uint32_t *xr)
+                          const FX &x, int nx, uint32_t *xr, bool x_ready = false)
 {
     bar<T>();
     for (int k = ny + 1 + tid<T>(); k < yclear; k += T) yb[k] = 0u;
     addsub<T>(ctl, ny + 1, false, 0u, y, Bal80{ny}, StoreBal{yb, ny});
+    if (x_ready) return;
     addsub<T>(ctl, nx + 1, false, 0u, x, Bal80{nx}, StoreBalRev{xr, nx});
     // every read of x happened before addsub's internal barrier, and the pads
     // are disjoint from the digits written: no barrier needed here

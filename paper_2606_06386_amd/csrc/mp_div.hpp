@@ -50,9 +50,14 @@ MP_HD int hmax(int a, int b) { return a > b ? a : b; }
 // LDS layout of one division / shifted-inverse instance with h = prec(u)
 // (or the shinv precision) and k = prec(v) - 1, in 32-bit words.  Capacities
 // bound every intermediate of the method: w <= h-k+4 limbs, x <= k+8,
-// Refine products <= h+6, u*shinv <= 2h-k+1, shinv <= h-k+1.  R holds the
-// reversed digits of the shorter operand of a matrix-core product (up to
-// h/2 + 15 limbs); the window area SB doubles as the long operand's digits.
+// shinv <= h-k+1.  R holds the reversed digits of the shorter operand of a
+// matrix-core product (up to h/2 + 15 limbs); the window area SB doubles as
+// the long operand's digits.  P holds the columns a product forms, from its
+// first formed column on: PowDiff's close product (L <= k + 7 columns), the
+// Step's w x from column sh - 2 up (about m + 16 columns: within max(k, d) + 9
+// over a scan of random and structured operands of up to 700 limbs), u * shinv
+// from column h - 9 up (at most h - k + 11), the low k + 2 columns of v q0
+// and shinv's fix-up product (k + 4); every use is guarded.
 struct Plan {
     int capV, capW, capX, capR, capSB, capP;
     int offV, offW, offX, offR, offSB, offP;   // offR: word 0 of the reversed digits, offSB: limb 0 of the window
@@ -70,7 +75,7 @@ MP_HD Plan plan_div(int h, int k)
     p.capX = r4(k + 12);
     p.capR = r4(h / 2 + 16);
     p.capSB = r4(hmax(hmax(h, k + 12), d + 8) + 4);
-    p.capP = r4(hmax(2 * h - k + 1, h + 8) + 4);
+    p.capP = r4(hmax(k, d) + 24);
     p.offV = kCtlWords;
     p.offW = p.offV + p.capV;
     p.offX = p.offW + p.capW;
@@ -156,29 +161,31 @@ MP_HD int mul_lds_words(int na, int nb)
 template <int T, bool MF, class FL, class FS>
 MP_DEV int product_views(uint32_t *ctl, uint32_t *p, int ncols, const FL &lng, int nl, const uint32_t *lng_lds,
                          const FS &sht, int ns, const uint32_t *sht_lds, uint32_t *sb, int &sbext,
-                         uint32_t *xr, int xrcap, int mfma_min, int c0 = 0, bool want_prec = true)
+                         uint32_t *xr, int xrcap, int mfma_min, int c0 = 0, bool want_prec = true,
+                         bool sht_ready = false)
 {
     if constexpr (MF) {
         if (ns >= mfma_min && ns + 1 <= xrcap) {
-            mfma_operands<T>(ctl, lng, nl, sb, sbext, sht, ns, xr);
+            mfma_operands<T>(ctl, lng, nl, sb, sbext, sht, ns, xr, sht_ready);
             sbext = nl + 1;
             return mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0, want_prec);
         }
     }
     copy<T>(sb, nl, sbext, lng);
     sbext = nl;
-    return mul<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0, want_prec);
+    if constexpr (T == kLanes) return mul1<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0, want_prec);
+    else return mul<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0, want_prec);
 }
 
 template <int T, bool MF = true>
 MP_DEV int product(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *x, int nx,
                    const uint32_t *y, int ny, uint32_t *sb, int &sbext, uint32_t *xr, int xrcap, int mfma_min,
-                   int c0 = 0, bool want_prec = true)
+                   int c0 = 0, bool want_prec = true, bool sht_ready = false)
 {
     const uint32_t *sht = nx >= ny ? y : x, *lng = nx >= ny ? x : y;
     const int ns = nx >= ny ? ny : nx, nl = nx >= ny ? nx : ny;
     return product_views<T, MF>(ctl, p, ncols, Span{lng, 0, nl}, nl, lng, Span{sht, 0, ns}, ns, sht, sb, sbext,
-                                xr, xrcap, mfma_min, c0, want_prec);
+                                xr, xrcap, mfma_min, c0, want_prec, sht_ready);
 }
 
 // dst[0, n) = src limbs [0, e) zero-padded, where e = prec(src) must be <= n;
@@ -260,33 +267,40 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
         }
     }
     // Step: res = shift_m(w) +- shift_{2m-H}(w x); then w = shift_{-post}(res).
-    // Only the columns of w x from cs = sh - 2 (rounded down to a multiple
-    // of 8) up are formed: the columns below change the shifted product by
-    // less than one unit of the iterate's last guard limb, and the sticky
-    // bit of the negative branch is taken from the formed columns below sh.
-    // The matrix-core digits can make the dropped part negative, so the
-    // formed sum T may exceed w x: one more column holds T < 2 B^(nw+nx),
-    // and nw + nx >= sh + 2 keeps T > 0 (w x >= B^(nw+nx-2) exceeds the
-    // dropped part).
+    // When nw + nx <= sh, w x < B^sh: the shifted product is 0 and, in the
+    // negative branch, its nonzero low part borrows one; no product is formed.
+    // Otherwise only the columns of w x from cs = sh - 2 (rounded down to a
+    // multiple of 8) up are formed: the columns below change the shifted
+    // product by less than one unit of the iterate's last guard limb, and the
+    // sticky bit of the negative branch is taken from the formed columns below
+    // sh.  The matrix-core digits can make the dropped part negative (less
+    // than 2^17 cs B^cs in size), so the formed sum T may exceed w x: one more
+    // column holds T < 2 B^(nw+nx), and w x >= B^(nw+nx-2) >= B^(sh-1) keeps
+    // T > 0.
     const int sh = H - 2 * m;
     const int post = i < 2 ? m : 1;
     int nt = 0, cs = 0;
-    if (nx) {
+    uint32_t below = 0;   // borrow of a product that lies wholly below sh
+    if (nx && nw + nx <= sh) {
+        below = sign ? 0u : 1u;
+    } else if (nx) {
         nt = nw + nx;
-        cs = nt >= sh + 2 ? imax(sh - 2, 0) & ~7 : 0;
+        cs = imax(sh - 2, 0) & ~7;
         if (cs) nt += 1;
-        if (nt > pl.capP) return false;
-        product<T, MF>(ctl, P, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, kn.mfma_min, cs, false);
+        if (nt - cs > pl.capP) return false;
+        // w is the shorter operand of both products on the matrix cores: its
+        // digits from PowDiff's product are still in XR
+        const bool w_ready = MF && nvp >= nw && nw < nx && nw >= kn.mfma_min && nw + 1 <= pl.capR;
+        // column c of the product goes to P[c - cs]
+        product<T, MF>(ctl, P - cs, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, kn.mfma_min, cs, false, w_ready);
     }
-    uint32_t sticky = 0;
-    if (!sign && nt > cs) {
-        const int top = imin(sh, nt);
-        sticky = reduce_max<T>(ctl, top - cs, [&](int j) -> uint32_t { return P[cs + j] ? 1u : 0u; });
-    }
+    // the sticky borrow of the negative branch (any nonzero formed column
+    // below sh) is found by the Step's own addsub before its carry scan
+    const int stop = !sign && nt > cs ? imin(sh, nt) - cs : 0;
     const int nres = imax(nw + m, nt - sh) + 1;
     if (nres - post > pl.capW) return false;
-    const uint32_t co = addsub<T>(ctl, nres, !sign, sticky, Span{W, m, nw}, Span{P, -sh, imax(nt, 0)},
-                                  Store{W, post, pl.capW});
+    const uint32_t co = addsub<T>(ctl, nres, !sign, below, Span{W, m, nw}, Span{P, cs - sh, imax(nt - cs, 0)},
+                                  Store{W, post, pl.capW}, StickyAny<T>{P, stop});
     if (!sign && co) return false;
     we = nres - post;
     nw = read_prec<T>(ctl, post);
@@ -319,21 +333,53 @@ MP_HD int small_iters(int d, int limit)
     return n;
 }
 
+// floor(B^3 / V) for B <= V < B^2, by one wave (every lane gets the result):
+// the quotient is B^2 when V = B and below B^2 otherwise.  Its bits are found
+// six at a time from the top: in each round lane j tests whether the bits
+// known so far followed by j (and zeros below) times V is at most B^3; the
+// lanes that pass are 0 .. J (the product grows with j), so J is the next six
+// bits.  Ten rounds of six bits and one of four: exact integer arithmetic, no
+// division.
+MP_DEV void inv96_wave(uint64_t V, uint64_t &q, uint32_t &q64)
+{
+    q = 0;
+    q64 = 0;
+    if (V == (1ull << 32)) {
+        q64 = 1;
+        return;
+    }
+    const unsigned __int128 B3 = ((unsigned __int128)1) << 96;
+    const uint64_t j = (uint64_t)lane();
+    for (int sh = 58; sh >= 0; sh -= 6) {
+        const uint64_t c = q | (j << (sh < 4 ? 0 : sh));
+        const bool ok = (sh >= 4 || j < 16) && (unsigned __int128)c * V <= B3;
+        const uint64_t m = ballot(ok);
+        q |= (uint64_t)(63 - __builtin_clzll(m)) << (sh < 4 ? 0 : sh);
+        if (sh < 4) break;
+        if (sh == 4) sh = 6;   // the last round takes bits 3 .. 0
+    }
+}
+
 // Alg. 1's initial approximation w = shift_g(floor(B^3 / V)), V = v_{k-1} + v_k B:
 // w0 <= B^2 has 3 limbs (65 bits when V = B).  vtop points at v_{k-1}, v_k.
+// Computed by the first wave of the T threads.
 template <int T>
 MP_DEV void refine_init(uint32_t *ctl, const uint32_t *vtop, uint32_t *W, int &we, int &nw)
 {
     bar<T>();
-    if (tid<T>() == 0) {
+    if (T == kLanes || tid<T>() < kLanes) {
         const uint64_t Vt = ((uint64_t)vtop[1] << 32) | vtop[0];
-        const unsigned __int128 w0 = (((unsigned __int128)1) << 96) / Vt;
-        W[0] = 0u;
-        W[1] = 0u;
-        W[2] = (uint32_t)w0;
-        W[3] = (uint32_t)(w0 >> 32);
-        W[4] = (uint32_t)(w0 >> 64);
-        ctl[kCtlBcast + 1] = W[4] ? 5u : W[3] ? 4u : 3u;
+        uint64_t w0;
+        uint32_t w64;
+        inv96_wave(Vt, w0, w64);
+        if (lane() == 0) {
+            W[0] = 0u;
+            W[1] = 0u;
+            W[2] = (uint32_t)w0;
+            W[3] = (uint32_t)(w0 >> 32);
+            W[4] = w64;
+            ctl[kCtlBcast + 1] = w64 ? 5u : (w0 >> 32) ? 4u : 3u;
+        }
     }
     bar<T>();
     nw = (int)uniform(ctl[kCtlBcast + 1]);
@@ -409,6 +455,7 @@ MP_DEV void head_refine(uint32_t *lds, int h, const uint32_t *v, int nv, uint32_
     constexpr int T = kLanes;
     uint32_t *ctl = lds;
     const int k = wave_prec(v, nv) - 1, d = h - k, g = 2;
+    MP_WSTAMP(1);
     bool go = k >= 1 && d >= 2;
     if (go) go = !(wave_low(v, k + 1) == k && v[k] == 1u);
     const int ns = go ? small_iters(d, kn.small_limit) : 0;
@@ -423,9 +470,14 @@ MP_DEV void head_refine(uint32_t *lds, int h, const uint32_t *v, int nv, uint32_
     for (int i = lane(); i < pl.capW; i += T) W[i] = 0u;
     for (int i = lane() - kPad; i < pl.capSB + kPad; i += T) SB[i] = 0u;
     int we = 0, nw = 0, sbext = 0, l = 2;
+    MP_WSTAMP(2);
     refine_init<T>(ctl, V + (k - 1 - vbase), W, we, nw);
+    MP_WSTAMP(3);
     bool ok = true;
-    for (int i = 0; i < ns && ok; i++) ok = refine_iter<T, false>(ctl, pl, kn, lds, h, k, i, l, we, nw, sbext);
+    for (int i = 0; i < ns && ok; i++) {
+        ok = refine_iter<T, false>(ctl, pl, kn, lds, h, k, i, l, we, nw, sbext);
+        MP_WSTAMP(16 + (i & 15));
+    }
     ok = ok && kRecHdr + we <= nrec;
     wave_sync();
     if (!ok) {
@@ -443,12 +495,14 @@ MP_DEV void head_refine(uint32_t *lds, int h, const uint32_t *v, int nv, uint32_
         rec[7] = 0u;
         rec[0] = kRecValid;
     }
+    MP_WSTAMP(4);
 }
 
 // the head of a division (h = prec(u))
 MP_DEV void head_divrem(uint32_t *lds, const uint32_t *u, int nu, const uint32_t *v, int nv, uint32_t *rec, int nrec,
                         const Knobs &kn)
 {
+    MP_WSTAMP(0);
     head_refine(lds, wave_prec(u, nu), v, nv, rec, nrec, kn);
 }
 
@@ -686,11 +740,16 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
                 // limbs are floor(u s / B^h) or one less (one more on the matrix
                 // cores, whose digit products below c0 may be negative)
                 const int c0 = imax(h - 2, 0) & ~7;
-                const int np = product_views<T, true>(ctl, P, h + ns, Ug, h, nullptr, Span{S, 0, ns}, ns, S, SB, sbext,
-                                                XR, pl.capR, kn.mfma_min, c0);
+                good = h + ns - c0 <= pl.capP;
+            }
+            if (good) {
+                // column c of the product goes to P[c - c0]
+                const int c0 = imax(h - 2, 0) & ~7;
+                const int np = product_views<T, true>(ctl, P - c0, h + ns, Ug, h, nullptr, Span{S, 0, ns}, ns, S, SB,
+                                                      sbext, XR, pl.capR, kn.mfma_min, c0);
                 MP_STAMP(5);
                 const int nq0 = imax(np - h, 0);
-                copy<T>(W, nq0, we, Span{P, -h, h + ns});
+                copy<T>(W, nq0, we, Span{P, c0 - h, h + ns - c0});
                 we = nq0;
                 // With s within two of the shifted inverse (the Step products
                 // are clipped too), q - 4 <= q0 <= q + 3 and r0 = u - v q0 lies

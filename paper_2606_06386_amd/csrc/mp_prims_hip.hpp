@@ -21,9 +21,19 @@ static __device__ uint64_t mp_trace_buf[8192 * 32];
     do {                                                                                             \
         if (threadIdx.x == 0) mp_trace_buf[(size_t)blockIdx.x * 32 + (id)] = __builtin_readcyclecounter(); \
     } while (0)
+// MP_WSTAMP(id): the same for lane 0 of each wave, in the row of the wave's
+// global index (heads: one instance per wave)
+#define MP_WSTAMP(id)                                                                                          \
+    do {                                                                                                       \
+        const size_t wv_ = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;                          \
+        if ((threadIdx.x & 63) == 0 && wv_ < 8192) mp_trace_buf[wv_ * 32 + (id)] = __builtin_readcyclecounter(); \
+    } while (0)
 #else
 #define MP_STAMP(id) \
     do {             \
+    } while (0)
+#define MP_WSTAMP(id) \
+    do {              \
     } while (0)
 #endif
 
@@ -48,12 +58,29 @@ MP_DEV void sync() { __syncthreads(); }
 MP_DEV void wave_sync() { asm volatile("" ::: "memory"); }
 MP_DEV uint64_t ballot(bool p) { return __ballot(p); }
 
-// value held by lane-1 (lane 0 receives 0)
-MP_DEV uint32_t shfl_up1(uint32_t x)
+// DPP controls (GFX9 data-parallel primitives: a VALU source operand read
+// from another lane of the same wave, no LDS round trip)
+constexpr int kDppQuadSwap1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadSwap2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int kDppWaveShr1 = 0x138;      // lane i reads lane i - 1
+constexpr int kDppRowMirror = 0x140;     // lane i of a 16-lane row reads lane 15 - i
+constexpr int kDppRowHalfMirror = 0x141; // lane i of an 8-lane half row reads lane 7 - i
+constexpr int kDppRowBcast15 = 0x142;    // lane 15 of each row to the next row
+constexpr int kDppRowBcast31 = 0x143;    // lane 31 to rows 2 and 3
+
+// x of the lane the DPP control selects; lanes without a source (and rows
+// outside row_mask) receive 0
+template <int CTRL, int ROWS = 0xF>
+MP_DEV uint32_t dpp(uint32_t x)
 {
-    uint32_t y = __shfl_up(x, 1);
-    return lane() == 0 ? 0u : y;
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, false);
 }
+
+// value held by lane-1 (lane 0 receives 0)
+MP_DEV uint32_t shfl_up1(uint32_t x) { return dpp<kDppWaveShr1>(x); }
+
+// value held by lane-2 (lanes 0 and 1 receive 0)
+MP_DEV uint32_t shfl_up2(uint32_t x) { return dpp<kDppWaveShr1>(dpp<kDppWaveShr1>(x)); }
 
 MP_DEV uint32_t shfl_xor(uint32_t x, int m) { return __shfl_xor(x, m); }
 
@@ -89,6 +116,27 @@ MP_DEV void mac4(uint64_t (&lo)[4], uint32_t (&hi)[4], uint32_t a,
           "+v"(hi[0]), "+v"(hi[1]), "+v"(hi[2]), "+v"(hi[3]),
           "=&s"(c0), "=&s"(c1), "=&s"(c2), "=&s"(c3)
         : "v"(a), "v"(b0), "v"(b1), "v"(b2), "v"(b3));
+}
+
+// acc[r] += a_r * b_r for r = 0..3 (four independent 96-bit column sums, as
+// mac4 but with a different multiplier per sum; the same wait-state spacing)
+MP_DEV void mac4x(uint64_t (&lo)[4], uint32_t (&hi)[4], uint32_t a0, uint32_t b0, uint32_t a1, uint32_t b1,
+                  uint32_t a2, uint32_t b2, uint32_t a3, uint32_t b3)
+{
+    uint64_t c0, c1, c2, c3;
+    asm volatile(
+        "v_mad_u64_u32 %0, %8, %12, %13, %0\n\t"
+        "v_mad_u64_u32 %1, %9, %14, %15, %1\n\t"
+        "v_mad_u64_u32 %2, %10, %16, %17, %2\n\t"
+        "v_mad_u64_u32 %3, %11, %18, %19, %3\n\t"
+        "v_addc_co_u32_e64 %4, %8, 0, %4, %8\n\t"
+        "v_addc_co_u32_e64 %5, %9, 0, %5, %9\n\t"
+        "v_addc_co_u32_e64 %6, %10, 0, %6, %10\n\t"
+        "v_addc_co_u32_e64 %7, %11, 0, %7, %11"
+        : "+v"(lo[0]), "+v"(lo[1]), "+v"(lo[2]), "+v"(lo[3]),
+          "+v"(hi[0]), "+v"(hi[1]), "+v"(hi[2]), "+v"(hi[3]),
+          "=&s"(c0), "=&s"(c1), "=&s"(c2), "=&s"(c3)
+        : "v"(a0), "v"(b0), "v"(a1), "v"(b1), "v"(a2), "v"(b2), "v"(a3), "v"(b3));
 }
 
 // bytes [sel, sel + 4) of the 8-byte value hi:lo (sel in 0..3)
