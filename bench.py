@@ -104,34 +104,36 @@ TRAFFIC_SOURCES = ["paper_2606_06386_amd/csrc/mp_prims_hip.hpp", "paper_2606_063
                    "paper_2606_06386_amd/csrc/kernels.hip", "paper_2606_06386_amd/csrc/mpdiv.hip"]
 
 
-def write_traffic(fetch_csv, write_csv, workload_name, kernel="k_divrem<"):
+def write_traffic(fetch_csv, write_csv, workload_name, kernels=("k_head_divrem", "k_divrem<")):
     """profiles/k_divrem_<workload>_traffic.json from two rocprofv3 --pmc
     counter files (FETCH_SIZE, WRITE_SIZE) of `bench.py --copy-calibration`:
-    the kernel's mean KiB per dispatch, each scaled by what the same counter
-    reads for the 256 MiB device copy."""
+    the mean KiB per dispatch of each kernel of one launch (the head and the
+    per-instance kernel of mp_divrem_batch), summed, each counter scaled by
+    what it reads for the 256 MiB device copy."""
     import csv
     import hashlib
 
     def read(path, counter):
-        kern, copy = [], []
+        kern, copy = {k: [] for k in kernels}, []
         with open(path) as fh:
             for row in csv.DictReader(fh):
                 if row["Counter_Name"] != counter:
                     continue
                 v = float(row["Counter_Value"])
-                if kernel in row["Kernel_Name"]:
-                    kern.append(v)
+                hit = [k for k in kernels if k in row["Kernel_Name"]]
+                if hit:
+                    kern[hit[0]].append(v)
                 elif "copyBuffer" in row["Kernel_Name"]:
                     copy.append(v)
-        assert kern and copy, (path, counter, len(kern), len(copy))
-        return sum(kern) / len(kern), max(copy)    # the 256 MiB copy is the largest
+        assert all(kern.values()) and copy, (path, counter, {k: len(x) for k, x in kern.items()}, len(copy))
+        return sum(sum(x) / len(x) for x in kern.values()), max(copy)   # the 256 MiB copy is the largest
 
     f_k, f_c = read(fetch_csv, "FETCH_SIZE")
     w_k, w_c = read(write_csv, "WRITE_SIZE")
     nbytes = 256 << 20
     ff, wf = nbytes / 1024 / f_c, nbytes / 1024 / w_c
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s_), "rb").read() for s_ in TRAFFIC_SOURCES)).hexdigest()
-    rec = {"kernel": kernel, "workload": workload_name, "fetch_size_kib_per_dispatch": f_k,
+    rec = {"kernels": list(kernels), "workload": workload_name, "fetch_size_kib_per_dispatch": f_k,
            "write_size_kib_per_dispatch": w_k,
            "copy_calibration": {"bytes": nbytes, "fetch_size_kib": f_c, "write_size_kib": w_c},
            "fetch_factor": ff, "write_factor": wf, "traffic_bytes_per_dispatch": 1024 * (f_k * ff + w_k * wf),
@@ -144,7 +146,8 @@ def write_traffic(fetch_csv, write_csv, workload_name, kernel="k_divrem<"):
 
 def cpu_baseline(c, q_gpu, r_gpu, budget_s=10.0):
     """The oracle (plain C, OpenMP over instances) on a bounded sample of the
-    same workload; also checks the GPU results of the sample bit-exactly."""
+    same workload, on all host cores and on one; also checks the GPU results of
+    the sample bit-exactly."""
     import oracle
     u, v, nq = c["u"], c["v"], c["nq"]
     n = 32
@@ -156,8 +159,15 @@ def cpu_baseline(c, q_gpu, r_gpu, budget_s=10.0):
     qo, ro, so, used = oracle.divrem_threads(u[:n], v[:n], nq, v.shape[1])
     t = time.perf_counter() - t0
     exact = int(((qo == q_gpu[:n]).all(axis=1) & (ro == r_gpu[:n]).all(axis=1)).sum())
+    n1 = max(8, min(n, int(n / max(used, 1))))       # about the same CPU time on one core
+    t0 = time.perf_counter()
+    oracle.divrem_threads(u[:n1], v[:n1], nq, v.shape[1], nthreads=1)
+    t1 = time.perf_counter() - t0
+    info = host_info()
     return {"value": n / t, "unit": "div/s", "cores": int(used), "kind": "oracle",
-            "sample": f"first {n} of {len(u)} instances of {c['name']} (Knuth D, gcc -O2, OpenMP)"}, exact, n
+            "sample": f"first {n} of {len(u)} instances of {c['name']} (Knuth D, gcc -O2, OpenMP)",
+            "one_core": {"value": n1 / t1, "unit": "div/s", "sample": f"first {n1} instances"},
+            **info}, exact, n
 
 
 PROBES = ["v_mad_u64_u32", "v_mad_u64_u32+v_addc_co_u32", "v_mul_lo_u32+v_mul_hi_u32", "v_add_u32",
@@ -209,14 +219,126 @@ def _timed(fn, steps, stream):
     return elapsed, ms
 
 
-def roofline(W, ms, kernel, traffic, algo_bytes):
-    """Roofline object of a launch doing W limb products in ms milliseconds."""
-    ops = OPS_PER_LIMB_PRODUCT * W / (ms * 1e-3)
-    return {"bound": "mfma", "achieved": ops / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TFLOP/s",
-            "op": "int8 matrix operations (32 per 32x32-bit limb product)", "frac": ops / PEAK_INT8_OPS,
-            "traffic": traffic, "traffic_unit": "bytes/launch", "algorithmic_bytes": algo_bytes,
-            "kernel": kernel, "limb_products_per_s": W / (ms * 1e-3),
-            "valu_mad_peak_limb_products_per_s": PEAK_LIMB_PRODUCTS}
+def roofline(W, W_clipped, ms, kernel, traffic, algo_bytes):
+    """Roofline object of a launch of ms milliseconds.  W is the method's
+    algorithmic work (limb products of Alg. 1-3 at exact operand sizes, full
+    quotient and remainder products); W_clipped is what the kernels form.
+    The products run on the int8 matrix cores (32 int8 operations per limb
+    product), so achieved and peak are int8 operations per second; the
+    fraction of the vector-ALU multiply peak is given beside them."""
+    rate = W / (ms * 1e-3)
+    ops = OPS_PER_LIMB_PRODUCT * rate
+    return {"bound": "mfma", "achieved": ops / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "int8 TOP/s",
+            "frac": ops / PEAK_INT8_OPS, "traffic": traffic, "traffic_unit": "bytes/launch",
+            "algorithmic_bytes": algo_bytes, "kernel": kernel,
+            "work": "limb products of Alg. 1-3 at exact sizes (full u*shinv, v*q), 32 int8 ops each",
+            "limb_products_per_launch": W, "limb_products_per_s": rate,
+            "frac_clipped": OPS_PER_LIMB_PRODUCT * W_clipped / (ms * 1e-3) / PEAK_INT8_OPS,
+            "limb_products_per_launch_clipped": W_clipped,
+            "frac_valu_peak": rate / PEAK_LIMB_PRODUCTS, "valu_mad_peak_limb_products_per_s": PEAK_LIMB_PRODUCTS}
+
+
+def host_info():
+    """CPU model and core counts of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def time_divrem(binding, c, steps, warmup, stream):
+    """Device-resident batch of c, timed per launch with HIP events on the
+    launch stream; returns (elapsed s, sorted launch ms, q, r, status)."""
+    import torch
+    dev = torch.device("cuda:0")
+    u_h, v_h, nq = c["u"], c["v"], c["nq"]
+    batch = len(u_h)
+    u = torch.from_numpy(u_h.view(np.int32)).to(dev)
+    v = torch.from_numpy(v_h.view(np.int32)).to(dev)
+    q = torch.empty((batch, nq), dtype=torch.int32, device=dev)
+    r = torch.empty((batch, v_h.shape[1]), dtype=torch.int32, device=dev)
+    st = torch.empty(batch, dtype=torch.int32, device=dev)
+    for _ in range(warmup):
+        binding.divrem(u, v, out=(q, r, st), stream=stream)
+    torch.cuda.synchronize()
+    elapsed, ms = _timed(lambda: binding.divrem(u, v, out=(q, r, st), stream=stream), steps, stream)
+    return (elapsed, ms, q.cpu().numpy().view(np.uint32), r.cpu().numpy().view(np.uint32), st.cpu().numpy(),
+            (u, v, q, r, st))
+
+
+def time_end_to_end(binding, c, steps, stream):
+    """The same launches with the operands uploaded from pinned host memory
+    before and the results downloaded after each one (PCIe included)."""
+    import torch
+    u_h, v_h, nq = c["u"], c["v"], c["nq"]
+    batch = len(u_h)
+    pin = lambda a: torch.from_numpy(a.view(np.int32)).pin_memory()
+    uh, vh = pin(u_h), pin(v_h)
+    qh = torch.empty((batch, nq), dtype=torch.int32).pin_memory()
+    rh = torch.empty((batch, v_h.shape[1]), dtype=torch.int32).pin_memory()
+    sh = torch.empty(batch, dtype=torch.int32).pin_memory()
+    dev = torch.device("cuda:0")
+    u, v = torch.empty_like(uh, device=dev), torch.empty_like(vh, device=dev)
+    q, r, st = torch.empty_like(qh, device=dev), torch.empty_like(rh, device=dev), torch.empty_like(sh, device=dev)
+
+    def step():
+        u.copy_(uh, non_blocking=True)
+        v.copy_(vh, non_blocking=True)
+        binding.divrem(u, v, out=(q, r, st), stream=stream)
+        qh.copy_(q, non_blocking=True)
+        rh.copy_(r, non_blocking=True)
+        sh.copy_(st, non_blocking=True)
+    step()
+    torch.cuda.synchronize()
+    _, ms = _timed(step, steps, stream)
+    mean = sum(ms) / len(ms)
+    return {"ms": mean, "div_per_s": batch / (mean * 1e-3),
+            "bytes_per_launch": 4 * (u_h.size + v_h.size + qh.numel() + rh.numel() + batch),
+            "what": "H2D of u, v from pinned host memory + mp_divrem_batch + D2H of q, r, status per launch"}
+
+
+def time_mul(binding, na, nb, batch, steps, warmup, stream):
+    """mp_mul_batch of batch random na x nb-limb products: mean launch ms."""
+    import torch
+    g = torch.Generator(device="cuda:0").manual_seed(na * 131 + nb)
+    a = torch.randint(-2 ** 31, 2 ** 31, (batch, na), dtype=torch.int32, device="cuda:0", generator=g)
+    b = torch.randint(-2 ** 31, 2 ** 31, (batch, nb), dtype=torch.int32, device="cuda:0", generator=g)
+    for _ in range(warmup):
+        binding.mul(a, b, stream=stream)
+    torch.cuda.synchronize()
+    _, ms = _timed(lambda: binding.mul(a, b, stream=stream), steps, stream)
+    mean = sum(ms) / len(ms)
+    ops = OPS_PER_LIMB_PRODUCT * na * nb * batch / (mean * 1e-3)
+    return {"ms": mean, "batch": batch, "limb_products_per_s": na * nb * batch / (mean * 1e-3),
+            "achieved": ops / 1e12, "unit": "int8 TOP/s", "frac": ops / PEAK_INT8_OPS}
+
+
+def plain_result(c, elapsed, ms, q_h, r_h, status, steps):
+    """Per-configuration figures of a timed plain batch."""
+    u_h, v_h = c["u"], c["v"]
+    batch = len(u_h)
+    kmean = sum(ms) / len(ms)
+    W = limb_products(u_h, v_h, clipped=False)
+    Wc = limb_products(u_h, v_h)
+    algo_bytes = 4 * (u_h.size + v_h.size + q_h.size + r_h.size) + 4 * batch   # u, v in; q, r, status out
+    n = int(u_h.shape[1])
+    return {"workload": c["name"], "batch": batch, "kernel_ms": {"mean": kmean, "median": ms[len(ms) // 2],
+                                                                 "min": ms[0]},
+            "div_per_s": batch * steps / elapsed, "div_per_s_kernel": batch / (kmean * 1e-3),
+            "roofline": roofline(W, Wc, kmean, "k_head_divrem + k_divrem<%d>" % threads_for(n),
+                                 measured_traffic(c["name"]), algo_bytes),
+            "full_mult_equivalents_per_s": batch / (kmean * 1e-3) * (W / batch) / (n * n / 2),
+            "status_ok": int((status == 0).sum())}
 
 
 PHASES = [("load_prec", 0, 1), ("setup", 1, 2), ("initial_approx", 2, 3), ("one_wave_iters", 3, 4)]
@@ -379,7 +501,8 @@ def run_mixed(args):
         "tuned": {str(k): v for k, v in tuned.items()}, "tuned_now": fresh,
         "limb_products_per_launch": W,
         "limb_products_per_launch_full_products": ragged_limb_products(us, vs, clipped=False),
-        "roofline": roofline(W, kmean, "k_ragged (4 width classes)", None, algo_bytes),
+        "roofline": roofline(ragged_limb_products(us, vs, clipped=False), W, kmean,
+                             "k_ragged_prep + k_head_ragged + k_ragged (4 width classes)", None, algo_bytes),
         "status_ok": int((status == 0).sum()),
     }
     if not args.no_cpu_baseline:
@@ -464,6 +587,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", action="store_true", help="measure integer instruction issue rates instead")
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the product timings, the end-to-end run and the other precisions")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record of --config's workload from two counter files and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -501,41 +626,15 @@ def main():
     if args.config == "c5":
         run_serving(args)
         return
-    dev = torch.device("cuda:0")
-    c = workload(args.config)
-    u_h, v_h, nq = c["u"], c["v"], c["nq"]
-    batch = len(u_h)
-    u = torch.from_numpy(u_h.view(np.int32)).to(dev)
-    v = torch.from_numpy(v_h.view(np.int32)).to(dev)
-    q = torch.empty((batch, nq), dtype=torch.int32, device=dev)
-    r = torch.empty((batch, v_h.shape[1]), dtype=torch.int32, device=dev)
-    st = torch.empty(batch, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        binding.divrem(u, v, out=(q, r, st), stream=stream)
-    torch.cuda.synchronize()
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record(stream)
-        binding.divrem(u, v, out=(q, r, st), stream=stream)
-        ends[i].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kernel_ms = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
-    kmean = sum(kernel_ms) / len(kernel_ms)
-
-    status = st.cpu().numpy()
-    q_h, r_h = q.cpu().numpy().view(np.uint32), r.cpu().numpy().view(np.uint32)
-    W = limb_products(u_h, v_h)
-    algo_bytes = 4 * (u_h.size + v_h.size + q_h.size + r_h.size) + 4 * batch   # u, v in; q, r, status out
+    c = workload(args.config)
+    elapsed, ms, q_h, r_h, status, dev_bufs = time_divrem(binding, c, args.steps, args.warmup, stream)
+    res = plain_result(c, elapsed, ms, q_h, r_h, status, args.steps)
+    u_h, v_h = c["u"], c["v"]
+    batch = len(u_h)
     line = {
         "metric": METRIC,
-        "value": batch * args.steps / elapsed,
+        "value": res["div_per_s"],
         "unit": "div/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -547,20 +646,44 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": c["name"], "bits": c["bits"], "batch": batch, "nu": int(u_h.shape[1]),
-                   "nv": int(v_h.shape[1]), "nq": nq},
-        "kernel_ms": {"mean": kmean, "median": kernel_ms[len(kernel_ms) // 2], "min": kernel_ms[0]},
-        "limb_products_per_launch": W,
-        "limb_products_per_launch_full_products": limb_products(u_h, v_h, clipped=False),
-        "roofline": roofline(W, kmean, "k_divrem<%d>" % threads_for(u_h.shape[1]), measured_traffic(c["name"]),
-                             algo_bytes),
-        "status_ok": int((status == 0).sum()),
+                   "nv": int(v_h.shape[1]), "nq": c["nq"]},
+        "kernel_ms": res["kernel_ms"],
+        "roofline": res["roofline"],
+        "full_mult_equivalents_per_s": res["full_mult_equivalents_per_s"],
+        "status_ok": res["status_ok"],
         "knobs": knobs_now(),
     }
+    del dev_bufs
     if args.copy_calibration:
-        x = torch.empty(64 << 20, dtype=torch.int32, device=dev)
+        x = torch.empty(64 << 20, dtype=torch.int32, device="cuda:0")
         y = torch.ones_like(x)
         x.copy_(y)
         torch.cuda.synchronize()
+        del x, y
+    if not args.no_extras:
+        # the paper's Table 1 column: time of the batch of divisions over a batch
+        # of multiplications of the same precision and count
+        n = int(u_h.shape[1])
+        mul_full = time_mul(binding, n, n, batch, max(5, args.steps // 2), 3, stream)
+        mul_q = time_mul(binding, n, n // 2 + 1, batch, max(5, args.steps // 2), 3, stream)
+        line["mul"] = {"%dx%d" % (n, n): mul_full, "%dx%d" % (n, n // 2 + 1): mul_q}
+        line["t_div_over_t_mul"] = res["kernel_ms"]["mean"] / mul_full["ms"]
+        line["end_to_end"] = time_end_to_end(binding, c, max(5, args.steps // 2), stream)
+        if args.config == "c2":
+            # the other plain precisions, each checked against the oracle in full
+            import oracle
+            subs = {}
+            for name in ("c1", "c3"):
+                cs = workload(name)
+                el, ms2, q2, r2, st2, bufs = time_divrem(binding, cs, max(5, args.steps // 2), 3, stream)
+                sub = plain_result(cs, el, ms2, q2, r2, st2, max(5, args.steps // 2))
+                del bufs
+                if not args.no_cpu_baseline:
+                    qo, ro, so = oracle.divrem(cs["u"], cs["v"], nq=cs["nq"], nr=cs["v"].shape[1])
+                    ok = ((qo == q2).all(axis=1) & (ro == r2).all(axis=1) & (so == st2)).sum()
+                    sub["parity_sample"] = f"{int(ok)}/{len(q2)} bit-exact vs oracle"
+                subs[name] = sub
+            line["configs"] = subs
     if not args.no_serving:
         # serving latency beside the throughput: 10^4 requests of 2^15..2^18
         # bits arriving at 10^5 per second (outside the timed region)
@@ -570,9 +693,9 @@ def main():
         row, _ = serving_run(1e5, 10000)
         line["serving"] = row
     if not args.no_cpu_baseline:
-        cb, exact, n = cpu_baseline(c, q_h, r_h)
+        cb, exact, n_cpu = cpu_baseline(c, q_h, r_h)
         line["cpu_baseline"] = cb
-        line["parity_sample"] = f"{exact}/{n} bit-exact vs oracle"
+        line["parity_sample"] = f"{exact}/{n_cpu} bit-exact vs oracle"
     print(json.dumps(line), flush=True)
 
 
