@@ -453,6 +453,21 @@ def run_mixed(args):
     elapsed, ms = _timed(lambda: rb.run(stream), args.steps, stream)
     kmean = sum(ms) / len(ms)
 
+    # the same launch sequence captured once in a graph and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        rb.run()                                  # the side stream's fork set, outside capture
+        with torch.cuda.graph(g, stream=side):
+            rb.run()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    for _ in range(max(1, args.warmup // 4)):
+        g.replay()
+    _, gms = _timed(g.replay, args.steps, stream)
+    gmean = sum(gms) / len(gms)
+
     # the same divisions as four uniform launches (one per dividend width)
     groups = []
     for n in I.C4_WIDTHS:
@@ -497,8 +512,10 @@ def run_mixed(args):
         "config": {"workload": c["name"], "bits": "2^15..2^18 mixed", "batch": count,
                    "widths": list(I.C4_WIDTHS), "nv": "uniform in [ceil(n/4), n]"},
         "kernel_ms": {"mean": kmean, "median": ms[len(ms) // 2], "min": ms[0]},
+        "graph_replay_ms": {"mean": gmean, "median": gms[len(gms) // 2], "min": gms[0]},
         "uniform_launches_ms": {"mean": pmean, "min": pms[0]},
-        "tuned": {str(k): v for k, v in tuned.items()}, "tuned_now": fresh,
+        "ragged_over_uniform": pmean / kmean, "graph_over_uniform": pmean / gmean,
+        "tuned": tuned, "tuned_now": fresh,
         "limb_products_per_launch": W,
         "limb_products_per_launch_full_products": ragged_limb_products(us, vs, clipped=False),
         "roofline": roofline(ragged_limb_products(us, vs, clipped=False), W, kmean,
@@ -530,50 +547,70 @@ def run_mixed(args):
     print(json.dumps(line), flush=True)
 
 
-def serving_run(rate, count, ops=None, max_batch=2048, max_limbs=1 << 22):
-    """One serving run; returns its summary (latencies in ms)."""
+def serving_run(rate, count, ops=None, path="ragged", depth=3):
+    """One serving run of the 2^15..2^18-bit request trace at `rate` arrivals/s
+    through the ragged (continuous batching) or the plain per-width path;
+    returns its summary (latencies in ms, upload and download included)."""
     from paper_2606_06386_amd import inputs as I, serve
     c = ops if ops is not None else I.config_c5(rate, count=count)
     arrival = I.c5_arrivals(rate, count)
-    res = serve.serve(c["u"], c["v"], arrival, max_batch=max_batch, max_limbs=max_limbs)
+    res = serve.serve(c["u"][:count], c["v"][:count], arrival, path=path, depth=depth)
     lat = res["latency"] * 1e3
-    st = res["backend"].status.cpu().numpy()
-    return {"rate_per_s": rate, "requests": count, "div_per_s": res["div_per_s"],
+    st = res["requests"].status.numpy()
+    return {"path": path, "rate_per_s": rate, "requests": count, "div_per_s": res["div_per_s"],
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_batch": float(np.mean(res["batches"])), "batches": len(res["batches"]),
+            "host_launch_share": res["host_launch_s"] / max(res["span_s"], 1e-9),
             "status_ok": int((st == 0).sum())}, res
 
 
-def run_serving(args):
-    from paper_2606_06386_amd import inputs as I, tune
-    import torch
-    count = 10000
-    tune.ensure(log=lambda m: print(m, file=sys.stderr, flush=True))
-    ops = I.config_c5(1e3, count=count)
-    rows = []
-    for rate in (1e3, 1e4, 1e5, 1e6):
-        row, res = serving_run(rate, count, ops)
-        rows.append(row)
-        print(json.dumps(row), file=sys.stderr, flush=True)
-    # bit-exact sample of the last run against the oracle
+def serving_parity(ops, res, count, every=250):
+    """a sample of a serving run's results against the oracle"""
     import oracle
-    q, r, st = res["backend"].results()
-    js = list(range(0, count, max(1, count // 40)))
+    q, r, st = res["requests"].results()
+    js = list(range(0, count, every))
     exact = 0
     for j in js:
         qo, ro, so = oracle.divrem(ops["u"][j][None, :], ops["v"][j][None, :], nq=len(ops["u"][j]),
                                    nr=len(ops["v"][j]))
         exact += int(so[0] == st[j] and (qo[0] == q[j]).all() and (ro[0] == r[j]).all())
-    top = rows[-1]
+    return f"{exact}/{len(js)} bit-exact vs oracle"
+
+
+def serving_compare(count=10000, rates=(1e6,), parity=True):
+    """Serving and the plain path on the same arrival traces, and both as one
+    device-resident batch (throughput only)."""
+    from paper_2606_06386_amd import inputs as I, serve, tune
+    tune.ensure(log=lambda m: print(m, file=sys.stderr, flush=True))
+    ops = I.config_c5(1e3, count=count)
+    serving_run(1e5, 300, ops)                 # warm-up: first launches and allocations
+    serving_run(1e5, 300, ops, path="plain")
+    out = {"workload": "serve_2p15_2p18_n%d" % count, "rates": []}
+    for rate in rates:
+        row_s, res = serving_run(rate, count, ops)
+        row_p, res_p = serving_run(rate, count, ops, path="plain")
+        row = {"rate_per_s": rate, "serving": row_s, "plain": row_p,
+               "serving_over_plain": row_s["div_per_s"] / max(row_p["div_per_s"], 1e-9)}
+        if parity:
+            row["serving"]["parity_sample"] = serving_parity(ops, res, count)
+            row["plain"]["parity_sample"] = serving_parity(ops, res_p, count)
+        out["rates"].append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    out["all_at_once"] = {"ragged": serve.all_at_once(ops["u"], ops["v"], "ragged"),
+                          "plain_four_launches": serve.all_at_once(ops["u"], ops["v"], "plain")}
+    return out
+
+
+def run_serving(args):
+    res = serving_compare(rates=(1e3, 1e4, 1e5, 1e6))
+    top = res["rates"][-1]
     line = {
-        "metric": METRIC, "value": top["div_per_s"], "unit": "div/s", "n_gpus": 1, "steps": len(rows),
-        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "serve_2p15_2p18_n%d" % count, "bits": "2^x, x ~ U[15, 18]",
-                   "nv": "uniform in [ceil(n/8), n]", "arrivals": "Poisson", "max_batch": 2048,
-                   "max_limbs": 1 << 22},
-        "serving": rows,
-        "parity_sample": f"{exact}/{len(js)} bit-exact vs oracle (rate 1e6 run)",
+        "metric": METRIC, "value": top["serving"]["div_per_s"], "unit": "div/s", "n_gpus": 1,
+        "steps": len(res["rates"]), "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": res["workload"], "bits": "2^x, x ~ U[15, 18]", "nv": "uniform in [ceil(n/8), n]",
+                   "arrivals": "Poisson", "admission": "HBM free share and LDS residency", "depth": 3},
+        "serving": res,
     }
     print(json.dumps(line), flush=True)
 
@@ -685,13 +722,11 @@ def main():
                 subs[name] = sub
             line["configs"] = subs
     if not args.no_serving:
-        # serving latency beside the throughput: 10^4 requests of 2^15..2^18
-        # bits arriving at 10^5 per second (outside the timed region)
-        from paper_2606_06386_amd import tune
-        tune.ensure()
-        serving_run(1e5, 500)            # warm-up: first launches of the class kernels
-        row, _ = serving_run(1e5, 10000)
-        line["serving"] = row
+        # serving beside the throughput (outside the timed region): 10^4
+        # requests of 2^15..2^18 bits arriving at 10^6 per second, served with
+        # continuous batching and through the plain per-width path on the same
+        # trace; latency from arrival to results in host memory
+        line["serving"] = serving_compare(rates=(1e6,), parity=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         cb, exact, n_cpu = cpu_baseline(c, q_h, r_h)
         line["cpu_baseline"] = cb

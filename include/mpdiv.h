@@ -112,7 +112,12 @@ typedef struct {
  *              by the caller, not shared by concurrent calls;
  *   inst_status: count int32 (required).
  * Widths and offsets are checked on the device; null pointers and count < 0 on
- * the host.
+ * the host.  The class kernels run on library-owned fork streams joined back
+ * into `stream`; each caller stream (up to eight per device) gets its own set,
+ * so batches launched on different streams overlap on the device.  A stream
+ * first seen while it is being captured into a graph gets no set: the class
+ * kernels then run one after another on it (call once outside capture first
+ * to capture the concurrent form).
  */
 mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint32_t *v_pool, int64_t v_limbs,
                              const mp_desc_t *desc, uint32_t *q_pool, int64_t q_limbs, uint32_t *r_pool,
@@ -165,7 +170,7 @@ mp_status_t mp_ragged_config(int32_t cls, int32_t threads, int32_t wgs_per_cu);
  *                        limbs of the instance's q (mp_shinv_batch: w) row,
  *                        which the final result then overwrites.  0 (or an
  *                        output row shorter than 16 limbs) runs every step in
- *                        the per-instance workgroups.  Default 64.
+ *                        the per-instance workgroups.  Default 96.
  * mp_set_knob returns MP_ERR_ARG for an unknown knob or a value out of range;
  * mp_get_knob returns the current value (-1 for an unknown knob).
  */

@@ -18,7 +18,7 @@ constexpr int kMaxLimbs = 8192;
 constexpr int kLdsWords = 160 * 1024 / 4;   // gfx950: 160 KB of LDS per workgroup
 
 // run-time knobs (mp_set_knob)
-std::atomic<int32_t> g_mfma_min{64}, g_small_limit{64};
+std::atomic<int32_t> g_mfma_min{64}, g_small_limit{96};
 
 mp::Knobs knobs() { return mp::Knobs{g_mfma_min.load(), g_small_limit.load()}; }
 
@@ -383,20 +383,41 @@ mp_status_t mp_divrem_ragged(const uint32_t *u_pool, int64_t u_limbs, const uint
     std::lock_guard<std::mutex> lock(g_ragged_mu);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MP_ERR_DEVICE;
-    // per-device fork streams and events (default priority), made once
-    static Forks forks[64];
-    static bool made[64];
-    if (!made[dev]) {
-        for (int c = 0; c < kClasses; c++) {
-            if (hipStreamCreateWithFlags(&forks[dev].fs[c], hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&forks[dev].ev_join[c], hipEventDisableTiming) != hipSuccess)
-                return MP_ERR_LAUNCH;
+    // fork streams and events (default priority), one set per caller stream
+    // (up to kForkSets per device, made on first use), so batches launched on
+    // different streams run their class kernels side by side; further caller
+    // streams share the last set (correct, only serialised)
+    constexpr int kForkSets = 8;
+    static Forks forks[64][kForkSets];
+    static hipStream_t owner[64][kForkSets];
+    static int nsets[64];
+    hipStream_t st = (hipStream_t)stream;
+    int f = 0;
+    while (f < nsets[dev] && owner[dev][f] != st) f++;
+    if (f == nsets[dev]) {
+        // no set for this stream yet: none is made while the stream is being
+        // captured into a graph (the kernels then run in order on it)
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) != hipSuccess) return MP_ERR_LAUNCH;
+        if (cap != hipStreamCaptureStatusNone)
+            return ragged_launch(u_pool, u_limbs, v_pool, v_limbs, desc, q_pool, q_limbs, r_pool, r_limbs,
+                                 inst_status, count, (int32_t *)workspace, st, nullptr);
+        if (f == kForkSets) {
+            f = kForkSets - 1;
+        } else {
+            Forks &fk = forks[dev][f];
+            for (int c = 0; c < kClasses; c++) {
+                if (hipStreamCreateWithFlags(&fk.fs[c], hipStreamNonBlocking) != hipSuccess ||
+                    hipEventCreateWithFlags(&fk.ev_join[c], hipEventDisableTiming) != hipSuccess)
+                    return MP_ERR_LAUNCH;
+            }
+            if (hipEventCreateWithFlags(&fk.ev_fork, hipEventDisableTiming) != hipSuccess) return MP_ERR_LAUNCH;
+            owner[dev][f] = st;
+            nsets[dev] = f + 1;
         }
-        if (hipEventCreateWithFlags(&forks[dev].ev_fork, hipEventDisableTiming) != hipSuccess) return MP_ERR_LAUNCH;
-        made[dev] = true;
     }
     return ragged_launch(u_pool, u_limbs, v_pool, v_limbs, desc, q_pool, q_limbs, r_pool, r_limbs, inst_status,
-                         count, (int32_t *)workspace, (hipStream_t)stream, &forks[dev]);
+                         count, (int32_t *)workspace, st, &forks[dev][f]);
 }
 
 mp_status_t mp_divrem_ragged_static(const uint32_t *u_pool, int64_t u_limbs, const uint32_t *v_pool,

@@ -2,12 +2,18 @@
 
 For each dividend width class of mp_divrem_ragged (<= 1024, 2048, 4096, 8192
 limbs) it times a one-class batch of seeded random divisions under every
-valid (threads per workgroup, persistent workgroups per compute unit) and
-installs the fastest with mp_ragged_config.  Results are cached in a JSON
-file keyed by the device (architecture name and compute-unit count) and by a
-hash of the kernel sources, so a cache entry is never applied to a different
-chip or to changed kernels.  Timing runs on the GPU; nothing here computes
-any part of a division.
+valid (threads per workgroup, hence limbs per thread in the linear passes;
+persistent workgroups per compute unit) and installs the fastest with
+mp_ragged_config.  Then, on a seeded mixed batch, it times the two
+process-wide knobs of the method's schedule and product engine: where the
+Newton precision-doubling schedule hands over from the one-wave head to the
+per-instance workgroups (MP_KNOB_SMALL_LIMIT) and from which operand length
+products move from the vector ALU to the matrix cores (MP_KNOB_MFMA_MIN),
+and installs the fastest pair.  Results are cached in a JSON file keyed by
+the device (architecture name and compute-unit count) and by a hash of the
+kernel sources, so a cache entry is never applied to a different chip or to
+changed kernels.  Timing runs on the GPU; nothing here computes any part of
+a division, and every setting gives the same bits.
 """
 import hashlib
 import json
@@ -68,6 +74,31 @@ def _time(rb, reps):
     return e0.elapsed_time(e1) / reps
 
 
+SMALL_LIMITS = (32, 48, 64, 80, 96, 112, 128)
+MFMA_MINS = (32, 64, 96, 128)
+
+
+def tune_knobs(count=1024, reps=3, log=None):
+    """Time every (small_limit, mfma_min) pair on a seeded mixed batch (all four
+    width classes); installs and returns the fastest as {knob: value, 'ms': ms}."""
+    from . import binding, ragged
+    m = I.config_c4(index=np.arange(0, 8 * count, 8))
+    rb = binding.Ragged(ragged.pack(m["u"], m["v"]))
+    times = []
+    for sl in SMALL_LIMITS:
+        for mm in MFMA_MINS:
+            binding.set_knob(binding.MP_KNOB_SMALL_LIMIT, sl)
+            binding.set_knob(binding.MP_KNOB_MFMA_MIN, mm)
+            ms = _time(rb, reps)
+            times.append((ms, sl, mm))
+            if log:
+                log("knobs small_limit %d, mfma_min %d: %.3f ms" % (sl, mm, ms))
+    ms, sl, mm = min(times)
+    binding.set_knob(binding.MP_KNOB_SMALL_LIMIT, sl)
+    binding.set_knob(binding.MP_KNOB_MFMA_MIN, mm)
+    return {"small_limit": sl, "mfma_min": mm, "ms": ms}
+
+
 def tune(counts=(2048, 1024, 512, 256), reps=3, log=None):
     """Time every candidate per class; returns {cls: (threads, wgs_per_cu, ms)}."""
     from . import binding, ragged
@@ -89,9 +120,15 @@ def tune(counts=(2048, 1024, 512, 256), reps=3, log=None):
 
 
 def apply(entry):
+    """Install a cache entry: {'classes': {cls: (threads, wgs_per_cu, ms)},
+    'knobs': {'small_limit': .., 'mfma_min': ..}}."""
     from . import binding
-    for cls, (t, g, _) in entry.items():
+    for cls, (t, g, _) in entry["classes"].items():
         binding.ragged_config(int(cls), int(t), int(g))
+    kn = entry.get("knobs")
+    if kn:
+        binding.set_knob(binding.MP_KNOB_SMALL_LIMIT, int(kn["small_limit"]))
+        binding.set_knob(binding.MP_KNOB_MFMA_MIN, int(kn["mfma_min"]))
 
 
 def ensure(cache=DEFAULT_CACHE, log=None):
@@ -102,11 +139,12 @@ def ensure(cache=DEFAULT_CACHE, log=None):
     if os.path.exists(cache):
         with open(cache) as fh:
             data = json.load(fh)
-    if key in data:
-        apply({int(k): v for k, v in data[key].items()})
+    if key in data and "classes" in data[key]:
+        apply(data[key])
         return data[key], False
     best = tune(log=log)
-    data[key] = {str(k): list(v) for k, v in best.items()}
+    knobs = tune_knobs(log=log)
+    data[key] = {"classes": {str(k): list(v) for k, v in best.items()}, "knobs": knobs}
     try:
         with open(cache, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)

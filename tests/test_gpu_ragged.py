@@ -174,6 +174,7 @@ def test_ragged_graph_replay(mp):
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
+        rb.run()                         # the stream's fork set exists before capture
         with torch.cuda.graph(g, stream=s):
             rb.run()
     torch.cuda.current_stream().wait_stream(s)
@@ -215,5 +216,35 @@ def test_tuner_configs_give_identical_results(mp, tmp_path):
     cache = tmp_path / "tuned.json"
     entry, fresh = tune.ensure(cache=str(cache))
     assert fresh and cache.exists()
+    kn = entry["knobs"]
+    assert kn["small_limit"] in tune.SMALL_LIMITS and kn["mfma_min"] in tune.MFMA_MINS
+    assert mp.get_knob(mp.MP_KNOB_SMALL_LIMIT) == kn["small_limit"]
     entry2, fresh2 = tune.ensure(cache=str(cache))
     assert not fresh2 and entry2 == entry
+
+
+def test_ragged_graph_of_a_fresh_stream(mp):
+    """Captured on a stream the library has not seen: the class kernels run in
+    order inside the graph, with the same results."""
+    import torch
+    c = I.config_c4(index=np.arange(300, 340))
+    rb = mp.Ragged(R.pack(c["u"], c["v"]))
+    rb.run()
+    torch.cuda.synchronize()
+    q0, r0, s0 = rb.q.clone(), rb.r.clone(), rb.status.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            rb.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        rb.q.zero_()
+        rb.r.zero_()
+        rb.status.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(rb.q, q0) and torch.equal(rb.r, r0) and torch.equal(rb.status, s0), rep

@@ -40,11 +40,12 @@ class FakeBackend:
         return h[1]
 
 
-def _serve(arrival, nlimbs, **kw):
+def _serve(arrival, nlimbs, max_batch, max_limbs, depth):
     clock = FakeClock()
-    be = FakeBackend(clock, np.asarray(nlimbs), depth=kw.get("depth", 2))
-    sch = Scheduler(be, nlimbs, **kw)
-    done_at, sizes = sch.run(arrival, clock=clock)
+    be = FakeBackend(clock, np.asarray(nlimbs), depth=depth)
+    sch = Scheduler(be, {"limbs": (nlimbs, max_limbs)}, max_batch=max_batch, depth=depth)
+    done_at, sizes, launch_s = sch.run(arrival, clock=clock)
+    assert launch_s >= 0
     return be, sch, done_at, sizes
 
 
@@ -73,13 +74,18 @@ def test_oversized_request_waits_then_is_admitted_alone():
     assert not np.isnan(done_at).any()
 
 
-def test_admit_respects_both_budgets():
+def test_admit_respects_every_budget():
     class Nop:
         pass
-    sch = Scheduler(Nop(), [10] * 100, max_batch=7, max_limbs=1000)
+    sch = Scheduler(Nop(), {"limbs": ([10] * 100, 1000)}, max_batch=7)
     assert sch.admit(list(range(20))) == list(range(7))
-    sch = Scheduler(Nop(), [300] * 100, max_batch=50, max_limbs=1000)
+    sch = Scheduler(Nop(), {"limbs": ([300] * 100, 1000)}, max_batch=50)
     assert sch.admit(list(range(20))) == [0, 1, 2]
+    # two budgets: the first one to run out ends the batch
+    sch = Scheduler(Nop(), {"hbm": ([100] * 100, 1000), "lds": ([0.3] * 100, 1.0)}, max_batch=50)
+    assert sch.admit(list(range(20))) == [0, 1, 2]
+    sch = Scheduler(Nop(), {"hbm": ([400] * 100, 1000), "lds": ([0.1] * 100, 1.0)}, max_batch=50)
+    assert sch.admit(list(range(20))) == [0, 1]
 
 
 def test_c5_workload_shapes():
