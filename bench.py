@@ -389,6 +389,14 @@ def phase_trace(args):
         prev = np.where(col > 0, col, prev)
         last = prev
     res["u_times_s"] = float(np.mean(rows[:, 5] - last))
+    # sub-steps of the last Refine iteration (stamps 11-13 hold its values)
+    it_end = [16 + i for i in range(16) if (rows[:, 16 + i] > 0).any()]
+    if len(it_end) >= 2 and (rows[:, [11, 12, 13]] > 0).all():
+        prev_end, end = rows[:, it_end[-2]], rows[:, it_end[-1]]
+        res["last_iter_powdiff_product"] = float(np.mean(rows[:, 11] - prev_end))
+        res["last_iter_residual"] = float(np.mean(rows[:, 12] - rows[:, 11]))
+        res["last_iter_step_product"] = float(np.mean(rows[:, 13] - rows[:, 12]))
+        res["last_iter_step_add"] = float(np.mean(end - rows[:, 13]))
     # the head launch (one wave per instance): its own stamps
     L.mp_trace_read_head.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.mp_trace_read_head.restype = ctypes.c_int
@@ -420,6 +428,37 @@ def phase_trace(args):
                       "instances": int(full.sum()),
                       "knobs": knobs_now(), "clock": "shader cycles (s_memtime) of workgroup thread 0",
                       "total_cycles": total, "cycles": res,
+                      "share": {k: v / total for k, v in res.items()}}), flush=True)
+
+
+def phase_trace_mul(args, na=2048, nb=2048, batch=4096):
+    """Per-phase cycle breakdown of one mp_mul_batch launch (the trace build):
+    clearing, digit conversion, the first wave's matrix-core strips, strip
+    carries, the copy out.  Prints one JSON line."""
+    import ctypes
+    import torch
+    from paper_2606_06386_amd import build as hb
+    hb.LIB = hb.TRACE_LIB
+    from paper_2606_06386_amd import binding
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    a = torch.randint(-2 ** 31, 2 ** 31, (batch, na), dtype=torch.int32, device="cuda:0", generator=g)
+    b = torch.randint(-2 ** 31, 2 ** 31, (batch, nb), dtype=torch.int32, device="cuda:0", generator=g)
+    for _ in range(3):
+        binding.mul(a, b)
+    torch.cuda.synchronize()
+    L = binding.lib()
+    L.mp_trace_read_mul.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.mp_trace_read_mul.restype = ctypes.c_int
+    st = np.zeros((batch, 32), dtype=np.uint64)
+    assert L.mp_trace_read_mul(st.ctypes.data, batch) == 0
+    st = st.astype(np.float64)
+    rows = st[(st[:, [0, 1, 2, 3, 4, 5, 10]] > 0).all(axis=1)]
+    ph = {"clear": (0, 1), "digit_conversion": (1, 2), "strips_first_wave": (2, 10), "strips_wait_and_carries": (10, 3),
+          "sync": (3, 4), "copy_out": (4, 5)}
+    res = {k: float(np.mean(rows[:, b_] - rows[:, a_])) for k, (a_, b_) in ph.items()}
+    total = float(np.mean(rows[:, 5] - rows[:, 0]))
+    print(json.dumps({"phase_trace": "mul %dx%d batch %d" % (na, nb, batch), "kernel": "k_mul<256>",
+                      "workgroups": len(rows), "total_cycles": total, "cycles": res,
                       "share": {k: v / total for k, v in res.items()}}), flush=True)
 
 
@@ -636,6 +675,8 @@ def main():
                     help="knob: Refine iterations with a shorter iterate run on one wave")
     ap.add_argument("--phase-trace", action="store_true",
                     help="per-phase cycle breakdown from the trace build of the library instead")
+    ap.add_argument("--phase-trace-mul", action="store_true",
+                    help="per-phase cycle breakdown of the 2048 x 2048-limb product kernel instead")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(*args.write_traffic, workload_name={"c1": "divrem_2p15_b1024", "c2": "divrem_2p16_b4096",
@@ -655,6 +696,9 @@ def main():
         return
     if args.phase_trace:
         phase_trace(args)
+        return
+    if args.phase_trace_mul:
+        phase_trace_mul(args)
         return
     set_knobs(args)
     if args.config == "c4":

@@ -253,6 +253,15 @@ extern "C" int mp_trace_read_head(uint64_t *dst, int waves)
 }
 #endif
 
+#if defined(MP_PHASE_TRACE) && MP_KFAMILY == 0 && MP_KT == 256
+// copies the stamps of the first `blocks` product workgroups (32 per workgroup) to host memory
+extern "C" int mp_trace_read_mul(uint64_t *dst, int blocks)
+{
+    return (int)hipMemcpyFromSymbol(dst, HIP_SYMBOL(mp_trace_buf), (size_t)blocks * 32 * sizeof(uint64_t), 0,
+                                    hipMemcpyDeviceToHost);
+}
+#endif
+
 #if defined(MP_PHASE_TRACE) && MP_KFAMILY == 2 && MP_KT == 256
 // copies the stamps of the first `blocks` workgroups (32 per workgroup) to host memory
 extern "C" int mp_trace_read_divrem(uint64_t *dst, int blocks)

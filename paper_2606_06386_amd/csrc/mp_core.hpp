@@ -787,6 +787,7 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
         }
         strip_resolve(ctl, s, base + s * kStrip, lo, hi, p, c0, ncols);
     }
+    MP_STAMP(10);   // the first wave's strips done
     return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base, want_prec);
 }
 

@@ -253,6 +253,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
     } else {                            // close product: P = v'w mod B^L
         if (L > pl.capP || L > pl.capX) return false;
         const int np = product<T, MF>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR, kn.mfma_min);
+        MP_STAMP(11);   // (trace build: sub-steps of the latest iteration)
         if (np == 0) {                  // v'w = B^hp exactly
             sign = true;
             nx = 0;
@@ -291,8 +292,10 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
         // w is the shorter operand of both products on the matrix cores: its
         // digits from PowDiff's product are still in XR
         const bool w_ready = MF && nvp >= nw && nw < nx && nw >= kn.mfma_min && nw + 1 <= pl.capR;
+        MP_STAMP(12);
         // column c of the product goes to P[c - cs]
         product<T, MF>(ctl, P - cs, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, kn.mfma_min, cs, false, w_ready);
+        MP_STAMP(13);
     }
     // the sticky borrow of the negative branch (any nonzero formed column
     // below sh) is found by the Step's own addsub before its carry scan
@@ -531,10 +534,14 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
     uint32_t *SB = SBbase + kPad;                   // long operand (window, or digits)
     uint32_t *P = SB + r4(nhi + 1) + kPad;
     int np;
+    MP_STAMP(0);
     if (nlo >= kn.mfma_min) {
         copy<T>(SBbase, 0, 2 * kPad + r4(nhi + 1), Zero{});
+        MP_STAMP(1);
         mfma_operands<T>(ctl, Span{lng, 0, nhi}, nhi, SB, 0, Span{sht, 0, nlo}, nlo, A);
+        MP_STAMP(2);
         np = mul_mfma<T>(ctl, P, na + nb, SB, nhi, A, nlo, 0, false);
+        MP_STAMP(3);
     } else {
         copy<T>(A, nlo, r4(nlo) + 4, Span{sht, 0, nlo});
         copy<T>(SBbase, kPad + nhi, 2 * kPad + r4(nhi), Span{lng, kPad, nhi});
@@ -542,7 +549,9 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
     }
     (void)np;
     bar<T>();
+    MP_STAMP(4);
     for (int i = tid<T>(); i < na + nb; i += T) c[i] = P[i];
+    MP_STAMP(5);
 }
 
 // w = floor(B^h / v), exactly (nw limbs).  rec: the head's record (at w), or
