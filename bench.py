@@ -659,7 +659,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "mul"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", action="store_true", help="measure integer instruction issue rates instead")
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving run")
@@ -706,6 +706,16 @@ def main():
         return
     if args.config == "c5":
         run_serving(args)
+        return
+    if args.config == "mul":
+        # the product the method is parameterised by, at 2^16 bits: full
+        # 2048 x 2048-limb products and the 2048 x 1025 shape of u * shinv
+        stream = torch.cuda.current_stream()
+        res = {n: time_mul(binding, a, b, 4096, args.steps, args.warmup, stream)
+               for n, (a, b) in {"2048x2048": (2048, 2048), "2048x1025": (2048, 1025)}.items()}
+        print(json.dumps({"metric": "mp_mul_batch limb products/s", "value": res["2048x2048"]["limb_products_per_s"],
+                          "unit": "limb products/s", "config": {"workload": "mul_2p16_b4096", "batch": 4096},
+                          "mul": res}), flush=True)
         return
     stream = torch.cuda.current_stream()
     c = workload(args.config)
