@@ -661,6 +661,13 @@ MP_DEV int mul1(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *a, int na
 // byte aligns); Y is one aligned 16-byte load per lane.  The accumulator of
 // lane (n, h) ends up holding the four byte sums of limb columns
 // 8n + 2q + h (q = 0..3) of the strip.
+//
+// X_d depends on d only, so a wave that owns two adjacent strips loads each
+// X_d once for both (the diagonal ranges of strips s and s+1 overlap in all
+// but 32 diagonals at each end).  The long operand's digits are held in two
+// planes of 16-byte half-blocks (plane h holds bytes 16h .. 16h+15 of every
+// 32-byte block), so the lanes of either half-wave read 32 consecutive
+// 16-byte chunks of one plane: the Y load has no bank conflicts.
 
 // (limb k of x) + 0x80808080 for k < n: the radix-256 balancing addend
 struct Bal80 {
@@ -668,11 +675,22 @@ struct Bal80 {
     MP_DEV uint32_t operator()(int k) const { return k < n ? 0x80808080u : 0u; }
 };
 
-// balanced digit limbs in natural order: dst[k], k in [0, n]
+constexpr int kYPadBlk = 31;   // zero blocks each digit plane needs on each side
+constexpr int kXPad = 16;      // zero words the reversed short operand needs on each side
+
+// words from the start of plane 0 to the start of plane 1 for an ny-limb long operand
+MP_DEV int mfma_plane(int ny) { return 4 * (((ny + 8) >> 3) + kYPadBlk); }
+// one past the last word of the planes that can be nonzero
+MP_DEV int mfma_ext(int ny) { return mfma_plane(ny) + 4 * ((ny + 8) >> 3); }
+
+// word of the planes holding limb k: block k / 8, plane (k / 4) % 2, word k % 4
+MP_DEV int plane_word(int k, int ly) { return ((k >> 1) & ~3) + (k & 3) + ((k >> 2) & 1) * ly; }
+
+// balanced digit limbs in the two planes: limb k, k in [0, n]
 struct StoreBal {
     uint32_t *p;
-    int n;
-    MP_DEV void operator()(int k, uint32_t z) const { p[k] = k < n ? z ^ 0x80808080u : z; }
+    int n, ly;
+    MP_DEV void operator()(int k, uint32_t z) const { p[plane_word(k, ly)] = k < n ? z ^ 0x80808080u : z; }
 };
 
 // balanced digit limbs byte-reversed: dst[n - k] = bytes of limb k reversed
@@ -682,15 +700,15 @@ struct StoreBalRev {
     MP_DEV void operator()(int k, uint32_t z) const { p[n - k] = bswap(k < n ? z ^ 0x80808080u : z); }
 };
 
-constexpr int kYPad = 248;   // zero limbs the long operand's digits need on each side (31 blocks)
-constexpr int kXPad = 16;    // zero words the reversed short operand needs on each side
-
-// Balanced digits of the long operand (ny limbs) into yb[0 .. ny] and of the
-// short operand (nx limbs) byte-reversed into xr[0 .. nx]; yb keeps kYPad zero
-// limbs below 0 and above its data (yb[ny+1 .. yclear) is cleared), xr gets
-// kXPad zero words on both sides.  The short operand must not live in xr's
-// padded range unless it is exactly the limbs the conversion reads first
-// (the reads all precede the writes inside addsub).
+// Balanced digits of the long operand (ny limbs) into the planes at yb and of
+// the short operand (nx limbs) byte-reversed into xr[0 .. nx].  Plane 0 holds
+// blocks [0, nb) at yb[0, 4 nb), nb = (ny + 8) / 8, plane 1 the same at
+// yb + mfma_plane(ny); each plane has kYPadBlk zero blocks on both sides (the
+// pad below plane 0 must already be zero; the rest up to mfma_ext(ny), and
+// the words from there up to yclear, are written here).  xr gets kXPad zero
+// words on both sides.  The short operand must not live in xr's padded range
+// unless it is exactly the limbs the conversion reads first (the reads all
+// precede the writes inside addsub).
 //
 // With x_ready the short operand's digits are already in xr (the same number
 // converted by an earlier call) and only the long operand is converted.
@@ -699,8 +717,14 @@ MP_DEV void mfma_operands(uint32_t *ctl, const FY &y, int ny, uint32_t *yb, int 
                           const FX &x, int nx, uint32_t *xr, bool x_ready = false)
 {
     bar<T>();
-    for (int k = ny + 1 + tid<T>(); k < yclear; k += T) yb[k] = 0u;
-    addsub<T>(ctl, ny + 1, false, 0u, y, Bal80{ny}, StoreBal{yb, ny});
+    const int nb = (ny + 8) >> 3, ly = mfma_plane(ny);
+    // the top block's limbs past the digits, the pad above plane 0 (= the pad
+    // below plane 1), the pad above plane 1 and what lies above it up to yclear
+    for (int k = ny + 1 + tid<T>(); k < 8 * nb; k += T) yb[plane_word(k, ly)] = 0u;
+    for (int k = tid<T>(); k < 4 * kYPadBlk; k += T) yb[4 * nb + k] = 0u;
+    const int hiend = imax(ly + 4 * nb + 4 * kYPadBlk, yclear);
+    for (int k = ly + 4 * nb + tid<T>(); k < hiend; k += T) yb[k] = 0u;
+    addsub<T>(ctl, ny + 1, false, 0u, y, Bal80{ny}, StoreBal{yb, ny, ly});
     if (x_ready) return;
     addsub<T>(ctl, nx + 1, false, 0u, x, Bal80{nx}, StoreBalRev{xr, nx});
     // every read of x happened before addsub's internal barrier, and the pads
@@ -711,12 +735,84 @@ MP_DEV void mfma_operands(uint32_t *ctl, const FY &y, int ny, uint32_t *yb, int 
     }
 }
 
+// X_d of this lane: 16 bytes of the reversed short digits from word xp on,
+// shifted by sft bytes (five words read, four byte aligns)
+struct XRaw {
+    uint32_t w0, w1, w2, w3, w4;
+};
+struct XFrag {
+    uint32_t a, b, c, d;
+};
+
+MP_DEV XRaw xraw(const uint32_t *xp) { return XRaw{xp[0], xp[1], xp[2], xp[3], xp[4]}; }
+MP_DEV XFrag xfrag(const XRaw &r, uint32_t sft)
+{
+    return XFrag{alignbyte(r.w1, r.w0, sft), alignbyte(r.w2, r.w1, sft), alignbyte(r.w3, r.w2, sft),
+                 alignbyte(r.w4, r.w3, sft)};
+}
+
+// Scheduling of one diagonal step: its LDS reads first (all in flight
+// together), then the vector ALU work (byte aligns, addresses), then the
+// matrix-core products; without this the scheduler of a kernel near its
+// register limit interleaves them and pays one LDS round trip per product.
+MP_DEV void sched_loads_first()
+{
+    __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);   // DS reads
+    __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);   // VALU
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);    // MFMA
+}
+
+MP_DEV MfmaAcc mfma_x(MfmaAcc acc, const XFrag &x, const Limb4 &y)
+{
+    return mfma_i8(acc, x.a, x.b, x.c, x.d, y.x, y.y, y.z, y.w);
+}
+
+// The limbs of strip s (its accumulator acc) into p, its carry into the strip slot
+MP_DEV void mfma_strip_out(uint32_t *ctl, const MfmaAcc &acc, int s, int base, uint32_t *p, int c0, int ncols)
+{
+    const int l = lane(), t = l & 31, h = l >> 5;
+    // limb columns 8t + 2q + h of the strip, biased to be non-negative: column
+    // base gets 2^56, every other column 2^56 - 2^24 (the biases telescope to
+    // 2^24 B^ncols, i.e. to 0 mod B^ncols)
+    uint32_t tl[4], th[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int64_t m = (int64_t)mfma_get(acc, 4 * q) + (int64_t)mfma_get(acc, 4 * q + 1) * 256 +
+                          (int64_t)mfma_get(acc, 4 * q + 2) * 65536 + (int64_t)mfma_get(acc, 4 * q + 3) * 16777216;
+        const int col = s * kStrip + 8 * t + 2 * q + h;   // relative to base
+        const uint64_t v = (uint64_t)(m + (col == 0 ? ((int64_t)1 << 56) : ((int64_t)1 << 56) - ((int64_t)1 << 24)));
+        tl[q] = (uint32_t)v;
+        th[q] = (uint32_t)(v >> 32);
+    }
+    // regroup: lane l takes columns 4l .. 4l+3; column 4l + j sits in lane
+    // (l >> 1) + 32 (j & 1), slot q = 2 (l & 1) + (j >> 1)
+    uint64_t lo[4];
+    const uint32_t hi[4] = {0u, 0u, 0u, 0u};
+    const int par = l & 1;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int src = (l >> 1) + 32 * (j & 1);
+        const uint32_t al = shfl(tl[j >> 1], src), ah = shfl(th[j >> 1], src);
+        const uint32_t bl = shfl(tl[2 + (j >> 1)], src), bh = shfl(th[2 + (j >> 1)], src);
+        lo[j] = par ? (((uint64_t)bh << 32) | bl) : (((uint64_t)ah << 32) | al);
+    }
+    strip_resolve(ctl, s, base + s * kStrip, lo, hi, p, c0, ncols);
+}
+
 // p[c0, ncols) = the columns c0 .. ncols-1 of x * y (as mul, c0 a multiple
-// of 8) from the digits prepared by mfma_operands (yb: ny+1 limbs of the long
-// operand, xr: nx+1 reversed limbs of the short); returns the precision of the
-// result.  With c0 > 0 the columns are those of the balanced radix-256 digit
-// products, T = sum of M_k 256^k over byte columns k >= 4 c0, which differs
-// from the limb-product sum by less than 2^16 c0 B^c0 in either direction.
+// of 8) from the digits prepared by mfma_operands (yb: the planes of the ny+1
+// digit limbs of the long operand, xr: nx+1 reversed limbs of the short);
+// returns the precision of the result.  With c0 > 0 the columns are those of
+// the balanced radix-256 digit products, T = sum of M_k 256^k over byte
+// columns k >= 4 c0, which differs from the limb-product sum by less than
+// 2^16 c0 B^c0 in either direction.
+//
+// A wave takes two of its strips sa < sb at a time: diagonals only sa
+// reaches, then those both reach (one X_d, two Y loads, two products), then
+// those only sb reaches.  With at least two pairs of adjacent strips per wave
+// the pairs are (2q, 2q + 1), dealt round robin (pair q to wave q mod W);
+// otherwise wave w keeps strips w, w + W, w + 2W, ... and pairs them in that
+// order (strips W apart share the diagonals where their ranges overlap).
 template <int T>
 MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, int ny,
                     const uint32_t *xr, int nx, int c0 = 0, bool want_prec = true)
@@ -731,61 +827,84 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
     const int nyblk = (ny + 1 + 7) >> 3;          // 32-byte blocks of the long digits
     const int R0 = 4 * (nx + 1) - 1;              // reversed byte x holds digit R0 - x
     const int dmax = (4 * (nx + 1) + 30) >> 5;    // last diagonal touching the short digits
-    for (int s = w; s < nstrips; s += W) {
-        const int S0 = 32 * s + (base >> 3);      // first 8-limb block of the strip
-        const int dlo = uniform(imax(0, S0 - nyblk + 1)), dhi = uniform(imin(dmax, S0 + 31));
-        MfmaAcc acc0 = mfma_zero(), acc1 = mfma_zero();
-        // Row t, half h of X_d starts at reversed byte R0 - 32 d - t + 16 h: its
-        // word address drops by 8 per diagonal and its byte shift is the same for
-        // every d.  Y_d's block address drops by 8 limbs per diagonal.
-        const int o0 = R0 - 32 * dlo - t + 16 * h;
-        const uint32_t sft = (uint32_t)o0 & 3u;
-        const uint32_t *xp = xr + (o0 >> 2);
-        const uint32_t *yp = yb + 8 * (S0 + t - dlo) + 4 * h;
-        int d = dlo;
-        for (; d + 1 <= dhi; d += 2, xp -= 16, yp -= 16) {
-            // all reads of the pair of diagonals first, then its two products
-            const uint32_t a0 = xp[0], a1 = xp[1], a2 = xp[2], a3 = xp[3], a4 = xp[4];
-            const uint32_t b0 = xp[-8], b1 = xp[-7], b2 = xp[-6], b3 = xp[-5], b4 = xp[-4];
-            const Limb4 y0 = load4(yp), y1 = load4(yp - 8);
-            acc0 = mfma_i8(acc0, alignbyte(a1, a0, sft), alignbyte(a2, a1, sft), alignbyte(a3, a2, sft),
-                           alignbyte(a4, a3, sft), y0.x, y0.y, y0.z, y0.w);
-            acc1 = mfma_i8(acc1, alignbyte(b1, b0, sft), alignbyte(b2, b1, sft), alignbyte(b3, b2, sft),
-                           alignbyte(b4, b3, sft), y1.x, y1.y, y1.z, y1.w);
+    // Row t, half h of X_d starts at reversed byte R0 - 32 d - t + 16 h: word
+    // (ox >> 2) - 8 d with the same byte shift ox & 3 for every d.  Y_d of a
+    // strip whose first block is S0 is block S0 + t - d of plane h.
+    const int ox = R0 - t + 16 * h;
+    const uint32_t sft = (uint32_t)ox & 3u;
+    const uint32_t *x0 = xr + (ox >> 2);
+    const uint32_t *y0 = yb + h * mfma_plane(ny) + 4 * t;
+    // strips sa and (if sb < nstrips) sb > sa.  Where one strip runs alone its
+    // products alternate between two accumulators (the other strip's, which
+    // is zero before sb starts and free once sa is stored), so consecutive
+    // matrix-core products never wait for each other's result.
+    auto step = [&](int sa, int sb) {
+        const bool two = sb < nstrips;
+        const int SA = 32 * sa + (base >> 3), SB = 32 * sb + (base >> 3);   // first 8-limb blocks
+        const int dloA = uniform(imax(0, SA - nyblk + 1)), dhiA = uniform(imin(dmax, SA + 31));
+        const int dloB = two ? uniform(imax(0, SB - nyblk + 1)) : dhiA + 1;
+        const int dhiB = two ? uniform(imin(dmax, SB + 31)) : dhiA;
+        // diagonal d: X_d from x0 - 8 d, Y_d of strip sa from yA - 4 d, of sb from yB - 4 d
+        const uint32_t *yA = y0 + 4 * SA, *yB = y0 + 4 * SB;
+        MfmaAcc accA = mfma_zero(), accB = mfma_zero();
+        int d = dloA;
+        // strip sa alone: even diagonals into accA, odd ones into accB
+        const int eA = imin(dhiA, dloB - 1);
+        if (d + 1 <= eA) {
+            for (; d + 1 <= eA; d += 2) {
+                const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
+                const Limb4 y0v = load4(yA - 4 * d), y1v = load4(yA - 4 * d - 4);
+                    accA = mfma_x(accA, xfrag(r0, sft), y0v);
+                accB = mfma_x(accB, xfrag(r1, sft), y1v);
+                sched_loads_first();
+            }
+            accA = mfma_add(accA, accB);
+            accB = mfma_zero();
         }
-        if (d <= dhi) {
-            const uint32_t a0 = xp[0], a1 = xp[1], a2 = xp[2], a3 = xp[3], a4 = xp[4];
-            const Limb4 y0 = load4(yp);
-            acc0 = mfma_i8(acc0, alignbyte(a1, a0, sft), alignbyte(a2, a1, sft), alignbyte(a3, a2, sft),
-                           alignbyte(a4, a3, sft), y0.x, y0.y, y0.z, y0.w);
+        if (d <= eA) {
+            const XRaw r0 = xraw(x0 - 8 * d);
+            const Limb4 y0v = load4(yA - 4 * d);
+            accA = mfma_x(accA, xfrag(r0, sft), y0v);
+            sched_loads_first();
+            d++;
         }
-        const MfmaAcc acc = mfma_add(acc0, acc1);
-        // limb columns 8t + 2q + h of the strip, biased to be non-negative: column
-        // base gets 2^56, every other column 2^56 - 2^24 (the biases telescope to
-        // 2^24 B^ncols, i.e. to 0 mod B^ncols)
-        uint32_t tl[4], th[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int64_t m = (int64_t)mfma_get(acc, 4 * q) + (int64_t)mfma_get(acc, 4 * q + 1) * 256 +
-                              (int64_t)mfma_get(acc, 4 * q + 2) * 65536 + (int64_t)mfma_get(acc, 4 * q + 3) * 16777216;
-            const int col = s * kStrip + 8 * t + 2 * q + h;   // relative to base
-            const uint64_t v = (uint64_t)(m + (col == 0 ? ((int64_t)1 << 56) : ((int64_t)1 << 56) - ((int64_t)1 << 24)));
-            tl[q] = (uint32_t)v;
-            th[q] = (uint32_t)(v >> 32);
+        // both strips: one diagonal per step (its two products are independent)
+        for (; d <= dhiA; d++) {
+            const XRaw r0 = xraw(x0 - 8 * d);
+            const Limb4 ya0 = load4(yA - 4 * d), yb0 = load4(yB - 4 * d);
+            const XFrag xf = xfrag(r0, sft);
+            accA = mfma_x(accA, xf, ya0);
+            accB = mfma_x(accB, xf, yb0);
+            sched_loads_first();
         }
-        // regroup: lane l takes columns 4l .. 4l+3; column 4l + j sits in lane
-        // (l >> 1) + 32 (j & 1), slot q = 2 (l & 1) + (j >> 1)
-        uint64_t lo[4];
-        const uint32_t hi[4] = {0u, 0u, 0u, 0u};
-        const int par = l & 1;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int src = (l >> 1) + 32 * (j & 1);
-            const uint32_t al = shfl(tl[j >> 1], src), ah = shfl(th[j >> 1], src);
-            const uint32_t bl = shfl(tl[2 + (j >> 1)], src), bh = shfl(th[2 + (j >> 1)], src);
-            lo[j] = par ? (((uint64_t)bh << 32) | bl) : (((uint64_t)ah << 32) | al);
+        mfma_strip_out(ctl, accA, sa, base, p, c0, ncols);
+        if (!two) return;
+        // strip sb alone (from dloB on, if strip sa ended before it began)
+        d = imax(d, dloB);
+        if (d + 1 <= dhiB) {
+            accA = mfma_zero();
+            for (; d + 1 <= dhiB; d += 2) {
+                const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
+                const Limb4 y0v = load4(yB - 4 * d), y1v = load4(yB - 4 * d - 4);
+                    accB = mfma_x(accB, xfrag(r0, sft), y0v);
+                accA = mfma_x(accA, xfrag(r1, sft), y1v);
+                sched_loads_first();
+            }
+            accB = mfma_add(accB, accA);
         }
-        strip_resolve(ctl, s, base + s * kStrip, lo, hi, p, c0, ncols);
+        if (d <= dhiB) {
+            const XRaw r0 = xraw(x0 - 8 * d);
+            const Limb4 y0v = load4(yB - 4 * d);
+            accB = mfma_x(accB, xfrag(r0, sft), y0v);
+            sched_loads_first();
+        }
+        mfma_strip_out(ctl, accB, sb, base, p, c0, ncols);
+    };
+    const int npairs = (nstrips + 1) >> 1;
+    if (npairs >= 2 * W) {
+        for (int q = w; q < npairs; q += W) step(2 * q, 2 * q + 1);
+    } else {
+        for (int s = w; s < nstrips; s += 2 * W) step(s, s + W);
     }
     MP_STAMP(10);   // the first wave's strips done
     return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base, want_prec);

@@ -167,7 +167,7 @@ MP_DEV int product_views(uint32_t *ctl, uint32_t *p, int ncols, const FL &lng, i
     if constexpr (MF) {
         if (ns >= mfma_min && ns + 1 <= xrcap) {
             mfma_operands<T>(ctl, lng, nl, sb, sbext, sht, ns, xr, sht_ready);
-            sbext = nl + 1;
+            sbext = mfma_ext(nl);
             return mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0, want_prec);
         }
     }
