@@ -344,6 +344,29 @@ def plain_result(c, elapsed, ms, q_h, r_h, status, steps):
 PHASES = [("load_prec", 0, 1), ("setup", 1, 2), ("initial_approx", 2, 3), ("one_wave_iters", 3, 4)]
 
 
+RT_HZ = 100e6   # rate of the real-time counter (s_memrealtime)
+
+
+def clock_stats(c0, c1, r0, r1, event_ms=None):
+    """Shader clock and residency of a traced launch from per-workgroup cycle
+    stamps (c0, c1) and real-time stamps (r0, r1) at its start and end: the
+    mean shader clock (cycles over real time), the mean workgroup lifetime,
+    the span from the first start to the last end, and the mean number of
+    workgroups resident over that span.  With the launch's event time, the
+    real-time counter's rate is checked against the span."""
+    ok = (r1 > r0) & (c1 > c0)
+    c0, c1, r0, r1 = c0[ok], c1[ok], r0[ok], r1[ok]
+    span = float(r1.max() - r0.min())
+    out = {"workgroups": int(ok.sum()),
+           "shader_clock_ghz": float(np.mean((c1 - c0) / (r1 - r0))) * RT_HZ / 1e9,
+           "workgroup_lifetime_us": float(np.mean(r1 - r0)) / RT_HZ * 1e6,
+           "launch_span_us": span / RT_HZ * 1e6,
+           "resident_workgroups": float(np.sum(r1 - r0)) / span if span > 0 else 0.0}
+    if event_ms:
+        out["event_ms"] = event_ms
+    return out
+
+
 def phase_trace(args):
     """Per-phase cycle breakdown of one k_divrem launch over the workload,
     from the phase stamps of libmpdiv_trace.so (build.py --trace): shader
@@ -367,6 +390,11 @@ def phase_trace(args):
            torch.empty(batch, dtype=torch.int32, device=dev))
     for _ in range(max(1, args.warmup)):
         binding.divrem(u, v, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    binding.divrem(u, v, out=out)
+    e1.record()
     torch.cuda.synchronize()
     L = binding.lib()
     L.mp_trace_read_divrem.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -427,6 +455,7 @@ def phase_trace(args):
     print(json.dumps({"phase_trace": c["name"], "kernel": "k_divrem<256>", "head": head,
                       "instances": int(full.sum()),
                       "knobs": knobs_now(), "clock": "shader cycles (s_memtime) of workgroup thread 0",
+                      "body_clock": clock_stats(st[:, 0], st[:, 8], st[:, 14], st[:, 15], e0.elapsed_time(e1)),
                       "total_cycles": total, "cycles": res,
                       "share": {k: v / total for k, v in res.items()}}), flush=True)
 
@@ -446,6 +475,11 @@ def phase_trace_mul(args, na=2048, nb=2048, batch=4096):
     for _ in range(3):
         binding.mul(a, b)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    binding.mul(a, b)
+    e1.record()
+    torch.cuda.synchronize()
     L = binding.lib()
     L.mp_trace_read_mul.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.mp_trace_read_mul.restype = ctypes.c_int
@@ -457,9 +491,10 @@ def phase_trace_mul(args, na=2048, nb=2048, batch=4096):
           "sync": (3, 4), "copy_out": (4, 5)}
     res = {k: float(np.mean(rows[:, b_] - rows[:, a_])) for k, (a_, b_) in ph.items()}
     total = float(np.mean(rows[:, 5] - rows[:, 0]))
+    clk = clock_stats(st[:, 0], st[:, 5], st[:, 6], st[:, 7], e0.elapsed_time(e1))
     print(json.dumps({"phase_trace": "mul %dx%d batch %d" % (na, nb, batch), "kernel": "k_mul<256>",
                       "workgroups": len(rows), "total_cycles": total, "cycles": res,
-                      "share": {k: v / total for k, v in res.items()}}), flush=True)
+                      "share": {k: v / total for k, v in res.items()}, "clock": clk}), flush=True)
 
 
 def set_knobs(args):

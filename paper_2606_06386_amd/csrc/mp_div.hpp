@@ -534,6 +534,7 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
     uint32_t *SB = SBbase + kPad;                   // long operand (window, or digits)
     uint32_t *P = SB + r4(nhi + 1) + kPad;
     int np;
+    MP_RSTAMP(6);
     MP_STAMP(0);
     if (nlo >= kn.mfma_min) {
         copy<T>(SBbase, 0, 2 * kPad + r4(nhi + 1), Zero{});
@@ -552,6 +553,7 @@ MP_DEV void mul_instance(uint32_t *lds, const uint32_t *a, int na, const uint32_
     MP_STAMP(4);
     for (int i = tid<T>(); i < na + nb; i += T) c[i] = P[i];
     MP_STAMP(5);
+    MP_RSTAMP(7);
 }
 
 // w = floor(B^h / v), exactly (nw limbs).  rec: the head's record (at w), or
@@ -663,6 +665,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     // one pass over u and v: prec(u), prec(v), and the lowest nonzero limb of v
     uint32_t red[3] = {0u, 0u, 0u};
     bar<T>();
+    MP_RSTAMP(14);
     MP_STAMP(0);
     {
         // eight limbs of u and of v per thread and step, all read before use;
@@ -812,6 +815,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     }
     if (status && tid<T>() == 0) *status = st;
     MP_STAMP(8);
+    MP_RSTAMP(15);
 }
 
 }  // namespace mp

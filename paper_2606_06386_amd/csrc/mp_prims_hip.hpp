@@ -17,9 +17,15 @@
 // mp_trace_buf (one per translation unit, for up to 8192 workgroups).
 #ifdef MP_PHASE_TRACE
 static __device__ uint64_t mp_trace_buf[8192 * 32];
-#define MP_STAMP(id)                                                                                 \
-    do {                                                                                             \
-        if (threadIdx.x == 0) mp_trace_buf[(size_t)blockIdx.x * 32 + (id)] = __builtin_readcyclecounter(); \
+#define MP_STAMP(id)                                                                                          \
+    do {                                                                                                      \
+        if (threadIdx.x == 0 && blockIdx.x < 8192) mp_trace_buf[(size_t)blockIdx.x * 32 + (id)] = __builtin_readcyclecounter(); \
+    } while (0)
+// MP_RSTAMP(id): the constant-rate (100 MHz) real-time counter instead, which
+// gives the shader clock rate of the run against the cycle stamps
+#define MP_RSTAMP(id)                                                                                         \
+    do {                                                                                                      \
+        if (threadIdx.x == 0 && blockIdx.x < 8192) mp_trace_buf[(size_t)blockIdx.x * 32 + (id)] = __builtin_amdgcn_s_memrealtime(); \
     } while (0)
 // MP_WSTAMP(id): the same for lane 0 of each wave, in the row of the wave's
 // global index (heads: one instance per wave)
@@ -33,6 +39,9 @@ static __device__ uint64_t mp_trace_buf[8192 * 32];
     do {             \
     } while (0)
 #define MP_WSTAMP(id) \
+    do {              \
+    } while (0)
+#define MP_RSTAMP(id) \
     do {              \
     } while (0)
 #endif
