@@ -74,8 +74,12 @@ mp_status_t mp_shinv_batch(const uint32_t *v, int32_t nv, int32_t h, uint32_t *w
 
 /*
  * Quotient and remainder of u by v for each instance (Alg. 3: the quotient
- * from u times the shifted inverse of v, then at most one downward and two
- * upward corrections).
+ * q0 from the top limbs of u times the shifted inverse of v, then
+ * corrections.  Theorem 2's range for q0, widened by the clipped products,
+ * is q - 4 <= q0 <= q + 3, so the remainder u - v q0 reaches [0, v) after at
+ * most three additions or four subtractions of v; one more of each is
+ * allowed, and an instance needing more reports MP_INST_INTERNAL instead of
+ * a wrong result).
  *   u: batch x nu limbs, v: batch x nv limbs, 1 <= nu, nv <= mp_max_limbs();
  *   q: batch x nq limbs, zero-padded; nq >= nu - prec(v) + 1 suffices (nu always);
  *   r: batch x nv limbs, zero-padded;
