@@ -452,7 +452,22 @@ def phase_trace(args):
     res["corrections"] = float(np.mean(rows[:, 7] - rows[:, 6]))
     res["store"] = float(np.mean(rows[:, 8] - rows[:, 7]))
     total = float(np.mean(rows[:, 8] - rows[:, 0]))
-    print(json.dumps({"phase_trace": c["name"], "kernel": "k_divrem<256>", "head": head,
+    # every product of the body: shape, conversion, strips of the first wave, carries
+    L.mp_trace_read_products.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.mp_trace_read_products.restype = ctypes.c_int
+    pt = np.zeros((batch, 48, 6), dtype=np.uint64)
+    assert L.mp_trace_read_products(pt.ctypes.data, batch) == 0
+    prods = []
+    ref = pt[np.flatnonzero(full)[0]]
+    for j in range(48):
+        r = pt[full][:, j, :].astype(np.float64)
+        if not (r[:, 2] > 0).all() or not (r[:, 5] >= r[:, 2]).all():
+            break
+        sh0, sh1 = int(ref[j, 0]), int(ref[j, 1])
+        prods.append({"short": sh0 & 0xFFFFFFFF, "long": sh0 >> 32, "ncols": sh1 & 0xFFFFFFFF, "c0": sh1 >> 32,
+                      "operands": float(np.mean(r[:, 3] - r[:, 2])), "strips": float(np.mean(r[:, 4] - r[:, 3])),
+                      "carries": float(np.mean(r[:, 5] - r[:, 4])), "total": float(np.mean(r[:, 5] - r[:, 2]))})
+    print(json.dumps({"phase_trace": c["name"], "kernel": "k_divrem<256>", "head": head, "products": prods,
                       "instances": int(full.sum()),
                       "knobs": knobs_now(), "clock": "shader cycles (s_memtime) of workgroup thread 0",
                       "body_clock": clock_stats(st[:, 0], st[:, 8], st[:, 14], st[:, 15], e0.elapsed_time(e1)),

@@ -269,4 +269,10 @@ extern "C" int mp_trace_read_divrem(uint64_t *dst, int blocks)
     return (int)hipMemcpyFromSymbol(dst, HIP_SYMBOL(mp_trace_buf), (size_t)blocks * 32 * sizeof(uint64_t), 0,
                                     hipMemcpyDeviceToHost);
 }
+// copies the product records of the first `blocks` workgroups (48 x 6 words each)
+extern "C" int mp_trace_read_products(uint64_t *dst, int blocks)
+{
+    return (int)hipMemcpyFromSymbol(dst, HIP_SYMBOL(mp_ptrace_buf), (size_t)blocks * 48 * 6 * sizeof(uint64_t), 0,
+                                    hipMemcpyDeviceToHost);
+}
 #endif

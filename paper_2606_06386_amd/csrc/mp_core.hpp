@@ -229,7 +229,7 @@ MP_DEV int cmp(uint32_t *ctl, int n, const FX &x, const FY &y)
 // nonzero limb, 0 for zero) is left in per-wave slots for read_prec.
 template <int T, int CM, class FX, class FY, class FO, class FS>
 MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin,
-                             const FX &x, const FY &y, const FO &out, const FS &stk)
+                             const FX &x, const FY &y, const FO &out, const FS &stk, int scan)
 {
     constexpr int W = T / kLanes;
     constexpr bool kPre = CM <= 9;   // short chunks: all reads first, so their latencies overlap
@@ -277,8 +277,8 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
         cout = (s0 < X ? 1u : 0u) | ((~P == 0 ? 1u : 0u) & cin);
     } else {
         if (lane() == 0) {
-            ctl[kCtlScan + 2 * w] = s0 < X ? 1u : 0u;      // wave generates
-            ctl[kCtlScan + 2 * w + 1] = (~P == 0) ? 1u : 0u;  // wave propagates
+            ctl[scan + 2 * w] = s0 < X ? 1u : 0u;      // wave generates
+            ctl[scan + 2 * w + 1] = (~P == 0) ? 1u : 0u;  // wave propagates
             if (FS::kActive) ctl[kCtlSticky + w] = SK ? 1u : 0u;
         }
         bar<T>();
@@ -291,7 +291,7 @@ MP_DEV uint32_t addsub_chunk(uint32_t *ctl, int n, int C, bool sub, uint32_t cin
 #pragma unroll
         for (int v = 0; v < W; v++) {
             if (v == w) cin_w = cout;
-            cout = ctl[kCtlScan + 2 * v] | (ctl[kCtlScan + 2 * v + 1] & cout);
+            cout = ctl[scan + 2 * v] | (ctl[scan + 2 * v + 1] & cout);
         }
     }
     const uint64_t cm = (X + G + (uint64_t)cin_w) ^ X ^ G;
@@ -358,23 +358,35 @@ struct StickyAny {
     }
 };
 
+// addsub without its leading barrier, for a caller that has just passed one
+// and touched nothing since that addsub reads or writes.  `scan` is the
+// control slot range of the wave summaries (2 words per wave): kCtlScan, or
+// kCtlRed for a second addsub that follows the first without a barrier (its
+// summaries must not overwrite those the first is still reading).
+template <int T, class FX, class FY, class FO, class FS = NoSticky>
+MP_DEV uint32_t addsub_nb(uint32_t *ctl, int n, bool sub, uint32_t cin,
+                          const FX &x, const FY &y, const FO &out, const FS &stk = FS{}, int scan = kCtlScan)
+{
+    // odd chunk length: lanes then touch LDS with an odd word stride (no bank conflicts)
+    const int C = ((n + T - 1) / T) | 1;
+    if (C == 1) return addsub_chunk<T, 1>(ctl, n, C, sub, cin, x, y, out, stk, scan);
+    if (C == 3) return addsub_chunk<T, 3>(ctl, n, C, sub, cin, x, y, out, stk, scan);
+    if (C <= 5) return addsub_chunk<T, 5>(ctl, n, C, sub, cin, x, y, out, stk, scan);
+    // a single wave (a head) handles at most kHeadMaxLimbs limbs per operation
+    if constexpr (T == kLanes) {
+        return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out, stk, scan);
+    } else {
+        if (C <= 9) return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out, stk, scan);
+        return addsub_chunk<T, kCMax>(ctl, n, C, sub, cin, x, y, out, stk, scan);
+    }
+}
+
 template <int T, class FX, class FY, class FO, class FS = NoSticky>
 MP_DEV uint32_t addsub(uint32_t *ctl, int n, bool sub, uint32_t cin,
                        const FX &x, const FY &y, const FO &out, const FS &stk = FS{})
 {
     bar<T>();
-    // odd chunk length: lanes then touch LDS with an odd word stride (no bank conflicts)
-    const int C = ((n + T - 1) / T) | 1;
-    if (C == 1) return addsub_chunk<T, 1>(ctl, n, C, sub, cin, x, y, out, stk);
-    if (C == 3) return addsub_chunk<T, 3>(ctl, n, C, sub, cin, x, y, out, stk);
-    if (C <= 5) return addsub_chunk<T, 5>(ctl, n, C, sub, cin, x, y, out, stk);
-    // a single wave (a head) handles at most kHeadMaxLimbs limbs per operation
-    if constexpr (T == kLanes) {
-        return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out, stk);
-    } else {
-        if (C <= 9) return addsub_chunk<T, 9>(ctl, n, C, sub, cin, x, y, out, stk);
-        return addsub_chunk<T, kCMax>(ctl, n, C, sub, cin, x, y, out, stk);
-    }
+    return addsub_nb<T>(ctl, n, sub, cin, x, y, out, stk);
 }
 
 // dst[k] = src(k) for k in [0, n), zero for k in [n, clear)
@@ -561,6 +573,7 @@ MP_DEV int mul(uint32_t *ctl, uint32_t *p, int ncols,
         }
         strip_resolve(ctl, s, K0, lo, hi, p, c0, ncols);
     }
+    MP_PT(4);
     return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base, want_prec);
 }
 
@@ -710,6 +723,10 @@ struct StoreBalRev {
 // unless it is exactly the limbs the conversion reads first (the reads all
 // precede the writes inside addsub).
 //
+// One barrier orders every earlier use of yb and xr before this; the two
+// conversions then follow each other without one (they read only x and y,
+// write disjoint digits, and keep their wave summaries in separate slots).
+//
 // With x_ready the short operand's digits are already in xr (the same number
 // converted by an earlier call) and only the long operand is converted.
 template <int T, class FY, class FX>
@@ -724,9 +741,9 @@ MP_DEV void mfma_operands(uint32_t *ctl, const FY &y, int ny, uint32_t *yb, int 
     for (int k = tid<T>(); k < 4 * kYPadBlk; k += T) yb[4 * nb + k] = 0u;
     const int hiend = imax(ly + 4 * nb + 4 * kYPadBlk, yclear);
     for (int k = ly + 4 * nb + tid<T>(); k < hiend; k += T) yb[k] = 0u;
-    addsub<T>(ctl, ny + 1, false, 0u, y, Bal80{ny}, StoreBal{yb, ny, ly});
+    addsub_nb<T>(ctl, ny + 1, false, 0u, y, Bal80{ny}, StoreBal{yb, ny, ly});
     if (x_ready) return;
-    addsub<T>(ctl, nx + 1, false, 0u, x, Bal80{nx}, StoreBalRev{xr, nx});
+    addsub_nb<T>(ctl, nx + 1, false, 0u, x, Bal80{nx}, StoreBalRev{xr, nx}, NoSticky{}, kCtlRed);
     // every read of x happened before addsub's internal barrier, and the pads
     // are disjoint from the digits written: no barrier needed here
     for (int k = tid<T>(); k < 2 * kXPad; k += T) {
@@ -907,6 +924,7 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
         for (int s = w; s < nstrips; s += 2 * W) step(s, s + W);
     }
     MP_STAMP(10);   // the first wave's strips done
+    MP_PT(4);
     return add_strip_carries<T>(ctl, p, c0, ncols, nstrips, base, want_prec);
 }
 

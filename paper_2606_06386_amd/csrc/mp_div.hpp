@@ -164,17 +164,25 @@ MP_DEV int product_views(uint32_t *ctl, uint32_t *p, int ncols, const FL &lng, i
                          uint32_t *xr, int xrcap, int mfma_min, int c0 = 0, bool want_prec = true,
                          bool sht_ready = false)
 {
+    MP_PT_BEGIN(ns, nl, ncols, c0);
+    int r;
     if constexpr (MF) {
         if (ns >= mfma_min && ns + 1 <= xrcap) {
             mfma_operands<T>(ctl, lng, nl, sb, sbext, sht, ns, xr, sht_ready);
+            MP_PT(3);
             sbext = mfma_ext(nl);
-            return mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0, want_prec);
+            r = mul_mfma<T>(ctl, p, ncols, sb, nl, xr, ns, c0, want_prec);
+            MP_PT_END();
+            return r;
         }
     }
     copy<T>(sb, nl, sbext, lng);
+    MP_PT(3);
     sbext = nl;
-    if constexpr (T == kLanes) return mul1<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0, want_prec);
-    else return mul<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0, want_prec);
+    if constexpr (T == kLanes) r = mul1<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0, want_prec);
+    else r = mul<T>(ctl, p, ncols, sht_lds, ns, sb, nl, c0, want_prec);
+    MP_PT_END();
+    return r;
 }
 
 template <int T, bool MF = true>
@@ -666,6 +674,7 @@ MP_DEV void divrem_instance(uint32_t *lds, const uint32_t *u, int nu, const uint
     uint32_t red[3] = {0u, 0u, 0u};
     bar<T>();
     MP_RSTAMP(14);
+    MP_PT_RESET();
     MP_STAMP(0);
     {
         // eight limbs of u and of v per thread and step, all read before use;

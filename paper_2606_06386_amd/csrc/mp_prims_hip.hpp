@@ -34,7 +34,55 @@ static __device__ uint64_t mp_trace_buf[8192 * 32];
         const size_t wv_ = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;                          \
         if ((threadIdx.x & 63) == 0 && wv_ < 8192) mp_trace_buf[wv_ * 32 + (id)] = __builtin_readcyclecounter(); \
     } while (0)
+// Product trace: for each product an instance forms (up to 48), thread 0
+// records its shape and the shader clock at its start, after the digit
+// conversion (or window copy), after the first wave's strips and at its end,
+// in 6 words of the workgroup's row of mp_ptrace_buf.  The running count
+// lives in LDS, touched by thread 0 only.
+static __device__ uint64_t mp_ptrace_buf[8192 * 48 * 6];
+__device__ __forceinline__ int &mp_ptrace_count()
+{
+    __shared__ int n;
+    return n;
+}
+#define MP_PT_RESET()                                                    \
+    do {                                                                 \
+        if (threadIdx.x == 0) mp_ptrace_count() = 0;                     \
+    } while (0)
+#define MP_PT_BEGIN(nx, ny, ncols, c0)                                                                       \
+    do {                                                                                                     \
+        const int n_ = mp_ptrace_count();                                                                    \
+        if (threadIdx.x == 0 && blockIdx.x < 8192 && n_ < 48) {                                             \
+            uint64_t *r_ = mp_ptrace_buf + ((size_t)blockIdx.x * 48 + n_) * 6;                               \
+            r_[0] = (uint64_t)(uint32_t)(nx) | ((uint64_t)(uint32_t)(ny) << 32);                             \
+            r_[1] = (uint64_t)(uint32_t)(ncols) | ((uint64_t)(uint32_t)(c0) << 32);                          \
+            r_[2] = __builtin_readcyclecounter();                                                            \
+        }                                                                                                    \
+    } while (0)
+#define MP_PT(slot)                                                                                          \
+    do {                                                                                                     \
+        const int n_ = mp_ptrace_count();                                                                    \
+        if (threadIdx.x == 0 && blockIdx.x < 8192 && n_ < 48)                                               \
+            mp_ptrace_buf[((size_t)blockIdx.x * 48 + n_) * 6 + (slot)] = __builtin_readcyclecounter();      \
+    } while (0)
+#define MP_PT_END()                                                                                          \
+    do {                                                                                                     \
+        MP_PT(5);                                                                                            \
+        if (threadIdx.x == 0) mp_ptrace_count() += 1;                                                        \
+    } while (0)
 #else
+#define MP_PT_RESET() \
+    do {              \
+    } while (0)
+#define MP_PT_BEGIN(nx, ny, ncols, c0) \
+    do {                               \
+    } while (0)
+#define MP_PT(slot) \
+    do {            \
+    } while (0)
+#define MP_PT_END() \
+    do {            \
+    } while (0)
 #define MP_STAMP(id) \
     do {             \
     } while (0)
