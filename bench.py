@@ -204,19 +204,43 @@ def probe_rates():
 
 
 def _timed(fn, steps, stream):
+    """Runs fn `steps` times back to back on `stream`; returns the wall time
+    of the whole run (synchronised on both sides) and the sorted durations of
+    the steps from HIP events.  One event marks each boundary between steps
+    (the end of one is the start of the next), so the instrumentation adds one
+    event record per step to the timed region, not two."""
     import torch
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks[0].record(stream)
     for i in range(steps):
-        starts[i].record(stream)
         fn()
-        ends[i].record(stream)
+        marks[i + 1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms = sorted(a.elapsed_time(b) for a, b in zip(starts, ends))
+    ms = sorted(a.elapsed_time(b) for a, b in zip(marks[:-1], marks[1:]))
     return elapsed, ms
+
+
+SETTLE_MS = 60.0   # untimed load before the warm-up steps (the shader clock's ramp lasts ~20-30 ms)
+
+
+def settle(fn, stream, min_ms=SETTLE_MS):
+    """Runs fn untimed until at least min_ms of wall time has passed, so that
+    the timed steps see the clock the chip holds under this load rather than
+    its ramp up from idle (step times fall by half over the first ~25 ms of
+    load).  Returns the number of steps run."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    while (time.perf_counter() - t0) * 1e3 < min_ms:
+        for _ in range(4):
+            fn()
+        n += 4
+        stream.synchronize()
+    return n
 
 
 def roofline(W, W_clipped, ms, kernel, traffic, algo_bytes):
@@ -268,12 +292,14 @@ def time_divrem(binding, c, steps, warmup, stream):
     q = torch.empty((batch, nq), dtype=torch.int32, device=dev)
     r = torch.empty((batch, v_h.shape[1]), dtype=torch.int32, device=dev)
     st = torch.empty(batch, dtype=torch.int32, device=dev)
+    step = lambda: binding.divrem(u, v, out=(q, r, st), stream=stream)
+    nset = settle(step, stream)
     for _ in range(warmup):
-        binding.divrem(u, v, out=(q, r, st), stream=stream)
+        step()
     torch.cuda.synchronize()
-    elapsed, ms = _timed(lambda: binding.divrem(u, v, out=(q, r, st), stream=stream), steps, stream)
+    elapsed, ms = _timed(step, steps, stream)
     return (elapsed, ms, q.cpu().numpy().view(np.uint32), r.cpu().numpy().view(np.uint32), st.cpu().numpy(),
-            (u, v, q, r, st))
+            (u, v, q, r, st), nset)
 
 
 def time_end_to_end(binding, c, steps, stream):
@@ -313,10 +339,12 @@ def time_mul(binding, na, nb, batch, steps, warmup, stream):
     g = torch.Generator(device="cuda:0").manual_seed(na * 131 + nb)
     a = torch.randint(-2 ** 31, 2 ** 31, (batch, na), dtype=torch.int32, device="cuda:0", generator=g)
     b = torch.randint(-2 ** 31, 2 ** 31, (batch, nb), dtype=torch.int32, device="cuda:0", generator=g)
+    step = lambda: binding.mul(a, b, stream=stream)
+    settle(step, stream)
     for _ in range(warmup):
-        binding.mul(a, b, stream=stream)
+        step()
     torch.cuda.synchronize()
-    _, ms = _timed(lambda: binding.mul(a, b, stream=stream), steps, stream)
+    _, ms = _timed(step, steps, stream)
     mean = sum(ms) / len(ms)
     ops = OPS_PER_LIMB_PRODUCT * na * nb * batch / (mean * 1e-3)
     return {"ms": mean, "batch": batch, "limb_products_per_s": na * nb * batch / (mean * 1e-3),
@@ -388,6 +416,7 @@ def phase_trace(args):
     out = (torch.empty((batch, nq), dtype=torch.int32, device=dev),
            torch.empty((batch, v_h.shape[1]), dtype=torch.int32, device=dev),
            torch.empty(batch, dtype=torch.int32, device=dev))
+    settle(lambda: binding.divrem(u, v, out=out), torch.cuda.current_stream())
     for _ in range(max(1, args.warmup)):
         binding.divrem(u, v, out=out)
     torch.cuda.synchronize()
@@ -487,6 +516,7 @@ def phase_trace_mul(args, na=2048, nb=2048, batch=4096):
     g = torch.Generator(device="cuda:0").manual_seed(7)
     a = torch.randint(-2 ** 31, 2 ** 31, (batch, na), dtype=torch.int32, device="cuda:0", generator=g)
     b = torch.randint(-2 ** 31, 2 ** 31, (batch, nb), dtype=torch.int32, device="cuda:0", generator=g)
+    settle(lambda: binding.mul(a, b), torch.cuda.current_stream())
     for _ in range(3):
         binding.mul(a, b)
     torch.cuda.synchronize()
@@ -537,6 +567,7 @@ def run_mixed(args):
     tuned, fresh = tune.ensure(log=lambda m: print(m, file=sys.stderr, flush=True))
     rb = binding.Ragged(R.pack(us, vs))
     stream = torch.cuda.current_stream()
+    nset = settle(lambda: rb.run(stream), stream)
     for _ in range(args.warmup):
         rb.run(stream)
     elapsed, ms = _timed(lambda: rb.run(stream), args.steps, stream)
@@ -592,6 +623,8 @@ def run_mixed(args):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle": {"min_ms": SETTLE_MS, "steps": nset,
+                   "what": "untimed steps before the warm-up, until the shader clock has left its ramp from idle"},
         "ms_per_step": elapsed * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
@@ -769,7 +802,7 @@ def main():
         return
     stream = torch.cuda.current_stream()
     c = workload(args.config)
-    elapsed, ms, q_h, r_h, status, dev_bufs = time_divrem(binding, c, args.steps, args.warmup, stream)
+    elapsed, ms, q_h, r_h, status, dev_bufs, nset = time_divrem(binding, c, args.steps, args.warmup, stream)
     res = plain_result(c, elapsed, ms, q_h, r_h, status, args.steps)
     u_h, v_h = c["u"], c["v"]
     batch = len(u_h)
@@ -780,6 +813,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle": {"min_ms": SETTLE_MS, "steps": nset,
+                   "what": "untimed steps before the warm-up, until the shader clock has left its ramp from idle"},
         "ms_per_step": elapsed * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
@@ -816,7 +851,7 @@ def main():
             subs = {}
             for name in ("c1", "c3"):
                 cs = workload(name)
-                el, ms2, q2, r2, st2, bufs = time_divrem(binding, cs, max(5, args.steps // 2), 3, stream)
+                el, ms2, q2, r2, st2, bufs, _ = time_divrem(binding, cs, max(5, args.steps // 2), 3, stream)
                 sub = plain_result(cs, el, ms2, q2, r2, st2, max(5, args.steps // 2))
                 del bufs
                 if not args.no_cpu_baseline:

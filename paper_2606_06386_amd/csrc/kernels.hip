@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kLanes * kHeadWaves) void k_head_shinv(const uint32
     const int wv = (int)(threadIdx.x / kLanes);
     const size_t j = (size_t)blockIdx.x * kHeadWaves + wv;
     if (j >= (size_t)batch) return;
-    head_refine(lds + wv * words, h, v + j * nv, nv, w + j * nw, nw, kn);
+    head_shinv(lds + wv * words, h, v + j * nv, nv, w + j * nw, nw, kn);
 }
 
 // heads of a ragged batch: wave g takes the g-th valid instance of the class

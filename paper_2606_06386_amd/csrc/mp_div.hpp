@@ -456,19 +456,20 @@ MP_DEV int wave_low(const uint32_t *x, int n)
     return n;
 }
 
-// The head of one instance with h and k = prec(v) - 1, by one wave in its own
-// LDS area (plan_head words): for the general case with h - k >= 2 and v not a
+// The head of one instance with h, k = prec(v) - 1 and vlow (index of v's
+// lowest nonzero limb), by one wave in its own LDS area (plan_head words):
+// for the general case with h - k >= 2 and v not a
 // power of B, Alg. 1's initial approximation and its Refine iterations while
 // the iterate is shorter than kn.small_limit limbs, recorded in rec[0, nrec);
 // otherwise (or when the state does not fit) rec[0] = 0.
-MP_DEV void head_refine(uint32_t *lds, int h, const uint32_t *v, int nv, uint32_t *rec, int nrec, const Knobs &kn)
+MP_DEV void head_refine(uint32_t *lds, int h, int k, int vlow, const uint32_t *v, uint32_t *rec, int nrec,
+                        const Knobs &kn)
 {
     constexpr int T = kLanes;
     uint32_t *ctl = lds;
-    const int k = wave_prec(v, nv) - 1, d = h - k, g = 2;
-    MP_WSTAMP(1);
+    const int d = h - k, g = 2;
     bool go = k >= 1 && d >= 2;
-    if (go) go = !(wave_low(v, k + 1) == k && v[k] == 1u);
+    if (go) go = !(vlow == k && v[k] == 1u);
     const int ns = go ? small_iters(d, kn.small_limit) : 0;
     const int vbase = ns ? imax(0, k - 2 * refine_l(d, ns - 1) + 1 - g) : 0;
     const Plan pl = plan_head(kn.small_limit, vbase);
@@ -477,7 +478,19 @@ MP_DEV void head_refine(uint32_t *lds, int h, const uint32_t *v, int nv, uint32_
         return;
     }
     uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *SB = lds + pl.offSB;
-    for (int i = lane(); i < k + 1 - vbase; i += T) V[i] = v[vbase + i];
+    // the divisor limbs [vbase, k]: four independent reads per lane in flight
+    // before their stores
+    {
+        const int nvs = k + 1 - vbase;
+        for (int i0 = lane(); i0 < nvs; i0 += 4 * T) {
+            uint32_t a[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) a[j] = i0 + j * T < nvs ? v[vbase + i0 + j * T] : 0u;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (i0 + j * T < nvs) V[i0 + j * T] = a[j];
+        }
+    }
     for (int i = lane(); i < pl.capW; i += T) W[i] = 0u;
     for (int i = lane() - kPad; i < pl.capSB + kPad; i += T) SB[i] = 0u;
     int we = 0, nw = 0, sbext = 0, l = 2;
@@ -509,12 +522,50 @@ MP_DEV void head_refine(uint32_t *lds, int h, const uint32_t *v, int nv, uint32_
     MP_WSTAMP(4);
 }
 
-// the head of a division (h = prec(u))
+// prec(x[0, n)) when x[0, n) is nonzero below its top 64 limbs or in them:
+// the ballot of the top chunk m (read by the caller) decides it, else the
+// scan goes on downwards
+MP_DEV int wave_prec_from(const uint32_t *x, int n, uint64_t m)
+{
+    if (m) return n - kLanes + 64 - __builtin_clzll(m);
+    return n > kLanes ? wave_prec(x, n - kLanes) : 0;
+}
+
+// k = prec(v) - 1 and the index of v's lowest nonzero limb, by one wave
+// from the ballots of v's top 64 limbs (mv) and bottom 64 limbs (mb), read
+// by the caller; a chunk of 64 zero limbs sends the scan on
+MP_DEV void wave_vshape(const uint32_t *v, int nv, uint64_t mv, uint64_t mb, int &k, int &vlow)
+{
+    k = wave_prec_from(v, nv, mv) - 1;
+    vlow = mb ? __builtin_ctzll(mb) : wave_low(v, k + 1);
+}
+
+// the head of a division (h = prec(u), k = prec(v) - 1): the top 64 limbs of
+// u and of v and the bottom 64 of v are read together, which settles both
+// precisions and v's lowest nonzero limb in one round trip unless a number
+// has 64 zero limbs at that end
 MP_DEV void head_divrem(uint32_t *lds, const uint32_t *u, int nu, const uint32_t *v, int nv, uint32_t *rec, int nrec,
                         const Knobs &kn)
 {
     MP_WSTAMP(0);
-    head_refine(lds, wave_prec(u, nu), v, nv, rec, nrec, kn);
+    const int iu = nu - kLanes + lane(), iv = nv - kLanes + lane(), il = lane();
+    const uint32_t ut = iu >= 0 ? u[iu] : 0u, vt = iv >= 0 ? v[iv] : 0u, vb = il < nv ? v[il] : 0u;
+    const uint64_t mu = ballot(ut != 0u), mv = ballot(vt != 0u), mb = ballot(vb != 0u);
+    const int h = wave_prec_from(u, nu, mu);
+    int k, vlow;
+    wave_vshape(v, nv, mv, mb, k, vlow);
+    MP_WSTAMP(1);
+    head_refine(lds, h, k, vlow, v, rec, nrec, kn);
+}
+
+// the head of a shifted inverse floor(B^h / v)
+MP_DEV void head_shinv(uint32_t *lds, int h, const uint32_t *v, int nv, uint32_t *rec, int nrec, const Knobs &kn)
+{
+    const int iv = nv - kLanes + lane(), il = lane();
+    const uint32_t vt = iv >= 0 ? v[iv] : 0u, vb = il < nv ? v[il] : 0u;
+    int k, vlow;
+    wave_vshape(v, nv, ballot(vt != 0u), ballot(vb != 0u), k, vlow);
+    head_refine(lds, h, k, vlow, v, rec, nrec, kn);
 }
 
 // a head record for (h, k) in the output row rec[0, nrec), or nullptr when rec
