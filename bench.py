@@ -487,13 +487,18 @@ def phase_trace(args):
     pt = np.zeros((batch, 48, 6), dtype=np.uint64)
     assert L.mp_trace_read_products(pt.ctypes.data, batch) == 0
     prods = []
-    ref = pt[np.flatnonzero(full)[0]]
+    ptf = pt[full]
+    ref = ptf[0]
     for j in range(48):
-        r = pt[full][:, j, :].astype(np.float64)
-        if not (r[:, 2] > 0).all() or not (r[:, 5] >= r[:, 2]).all():
+        # the instances whose j-th product has the reference instance's shape
+        same = (ptf[:, j, 0] == ref[j, 0]) & (ptf[:, j, 1] == ref[j, 1]) & (ptf[:, j, 5] >= ptf[:, j, 2]) & \
+            (ptf[:, j, 2] > 0)
+        if ref[j, 2] == 0 or not same.any():
             break
+        r = ptf[same][:, j, :].astype(np.float64)
         sh0, sh1 = int(ref[j, 0]), int(ref[j, 1])
         prods.append({"short": sh0 & 0xFFFFFFFF, "long": sh0 >> 32, "ncols": sh1 & 0xFFFFFFFF, "c0": sh1 >> 32,
+                      "instances": int(same.sum()),
                       "operands": float(np.mean(r[:, 3] - r[:, 2])), "strips": float(np.mean(r[:, 4] - r[:, 3])),
                       "carries": float(np.mean(r[:, 5] - r[:, 4])), "total": float(np.mean(r[:, 5] - r[:, 2]))})
     print(json.dumps({"phase_trace": c["name"], "kernel": "k_divrem<256>", "head": head, "products": prods,

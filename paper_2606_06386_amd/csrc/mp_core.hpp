@@ -871,7 +871,7 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
             for (; d + 1 <= eA; d += 2) {
                 const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
                 const Limb4 y0v = load4(yA - 4 * d), y1v = load4(yA - 4 * d - 4);
-                    accA = mfma_x(accA, xfrag(r0, sft), y0v);
+                accA = mfma_x(accA, xfrag(r0, sft), y0v);
                 accB = mfma_x(accB, xfrag(r1, sft), y1v);
                 sched_loads_first();
             }
@@ -903,7 +903,7 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
             for (; d + 1 <= dhiB; d += 2) {
                 const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
                 const Limb4 y0v = load4(yB - 4 * d), y1v = load4(yB - 4 * d - 4);
-                    accB = mfma_x(accB, xfrag(r0, sft), y0v);
+                accB = mfma_x(accB, xfrag(r0, sft), y0v);
                 accA = mfma_x(accA, xfrag(r1, sft), y1v);
                 sched_loads_first();
             }
