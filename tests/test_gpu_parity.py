@@ -60,9 +60,15 @@ def _stack(vals, n):
 
 # ------------------------------------------------------------------ mul
 
+# Shapes chosen to reach every way the matrix-core product deals its strips
+# to waves: strips W apart (fewer than two pairs per wave), adjacent pairs
+# (at least two), an odd strip left alone, pairs whose diagonal ranges do not
+# overlap (short operand of 64 limbs), at 256, 512 and 1024 threads.
 @pytest.mark.parametrize("na,nb", [(1, 1), (2, 3), (5, 300), (300, 5), (257, 256), (256, 257), (700, 1300),
                                    (1024, 1024), (64, 2048), (2048, 1025), (4093, 3), (4096, 4096),
-                                   (8192, 6145), (8192, 8192)])
+                                   (8192, 6145), (8192, 8192),
+                                   (2048, 2048), (2047, 2049), (2048, 1999), (2048, 1700), (1500, 2048), (64, 4096),
+                                   (3000, 4096), (4096, 2000), (5000, 8192), (64, 8192)])
 def test_mul_matches_oracle(mp, na, nb):
     import torch
     rng = np.random.default_rng(na * 7919 + nb)
