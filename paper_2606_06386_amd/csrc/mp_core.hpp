@@ -774,8 +774,8 @@ MP_DEV XFrag xfrag(const XRaw &r, uint32_t sft)
 // register limit interleaves them and pays one LDS round trip per product.
 MP_DEV void sched_loads_first()
 {
-    __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);   // DS reads
-    __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);   // VALU
+    __builtin_amdgcn_sched_group_barrier(0x100, 32, 0);   // DS reads
+    __builtin_amdgcn_sched_group_barrier(0x002, 32, 0);   // VALU
     __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);    // MFMA
 }
 
@@ -851,10 +851,11 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
     const uint32_t sft = (uint32_t)ox & 3u;
     const uint32_t *x0 = xr + (ox >> 2);
     const uint32_t *y0 = yb + h * mfma_plane(ny) + 4 * t;
-    // strips sa and (if sb < nstrips) sb > sa.  Where one strip runs alone its
-    // products alternate between two accumulators (the other strip's, which
-    // is zero before sb starts and free once sa is stored), so consecutive
-    // matrix-core products never wait for each other's result.
+    // strips sa and (if sb < nstrips) sb > sa.  Where one strip runs alone,
+    // a step keeps four diagonals' operands in flight and chains their
+    // products on the strip's accumulator (the other accumulator is not yet
+    // or no longer live there, which leaves the registers for the operands);
+    // where both run, a step is one diagonal whose X fragment feeds both.
     auto step = [&](int sa, int sb) {
         const bool two = sb < nstrips;
         const int SA = 32 * sa + (base >> 3), SB = 32 * sb + (base >> 3);   // first 8-limb blocks
@@ -865,25 +866,26 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
         const uint32_t *yA = y0 + 4 * SA, *yB = y0 + 4 * SB;
         MfmaAcc accA = mfma_zero(), accB = mfma_zero();
         int d = dloA;
-        // strip sa alone: even diagonals into accA, odd ones into accB
+        // strip sa alone: four diagonals' operands in flight per step, one
+        // accumulator (its chain of products costs about what the LDS round
+        // trip of the next step does)
         const int eA = imin(dhiA, dloB - 1);
-        if (d + 1 <= eA) {
-            for (; d + 1 <= eA; d += 2) {
-                const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
-                const Limb4 y0v = load4(yA - 4 * d), y1v = load4(yA - 4 * d - 4);
-                accA = mfma_x(accA, xfrag(r0, sft), y0v);
-                accB = mfma_x(accB, xfrag(r1, sft), y1v);
-                sched_loads_first();
-            }
-            accA = mfma_add(accA, accB);
-            accB = mfma_zero();
+        for (; d + 3 <= eA; d += 4) {
+            const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
+            const XRaw r2 = xraw(x0 - 8 * d - 16), r3 = xraw(x0 - 8 * d - 24);
+            const Limb4 y0v = load4(yA - 4 * d), y1v = load4(yA - 4 * d - 4);
+            const Limb4 y2v = load4(yA - 4 * d - 8), y3v = load4(yA - 4 * d - 12);
+            accA = mfma_x(accA, xfrag(r0, sft), y0v);
+            accA = mfma_x(accA, xfrag(r1, sft), y1v);
+            accA = mfma_x(accA, xfrag(r2, sft), y2v);
+            accA = mfma_x(accA, xfrag(r3, sft), y3v);
+            sched_loads_first();
         }
-        if (d <= eA) {
+        for (; d <= eA; d++) {
             const XRaw r0 = xraw(x0 - 8 * d);
             const Limb4 y0v = load4(yA - 4 * d);
             accA = mfma_x(accA, xfrag(r0, sft), y0v);
             sched_loads_first();
-            d++;
         }
         // both strips: one diagonal per step (its two products are independent)
         for (; d <= dhiA; d++) {
@@ -898,18 +900,18 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
         if (!two) return;
         // strip sb alone (from dloB on, if strip sa ended before it began)
         d = imax(d, dloB);
-        if (d + 1 <= dhiB) {
-            accA = mfma_zero();
-            for (; d + 1 <= dhiB; d += 2) {
-                const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
-                const Limb4 y0v = load4(yB - 4 * d), y1v = load4(yB - 4 * d - 4);
-                accB = mfma_x(accB, xfrag(r0, sft), y0v);
-                accA = mfma_x(accA, xfrag(r1, sft), y1v);
-                sched_loads_first();
-            }
-            accB = mfma_add(accB, accA);
+        for (; d + 3 <= dhiB; d += 4) {
+            const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
+            const XRaw r2 = xraw(x0 - 8 * d - 16), r3 = xraw(x0 - 8 * d - 24);
+            const Limb4 y0v = load4(yB - 4 * d), y1v = load4(yB - 4 * d - 4);
+            const Limb4 y2v = load4(yB - 4 * d - 8), y3v = load4(yB - 4 * d - 12);
+            accB = mfma_x(accB, xfrag(r0, sft), y0v);
+            accB = mfma_x(accB, xfrag(r1, sft), y1v);
+            accB = mfma_x(accB, xfrag(r2, sft), y2v);
+            accB = mfma_x(accB, xfrag(r3, sft), y3v);
+            sched_loads_first();
         }
-        if (d <= dhiB) {
+        for (; d <= dhiB; d++) {
             const XRaw r0 = xraw(x0 - 8 * d);
             const Limb4 y0v = load4(yB - 4 * d);
             accB = mfma_x(accB, xfrag(r0, sft), y0v);
