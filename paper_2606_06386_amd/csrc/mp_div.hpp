@@ -458,10 +458,10 @@ MP_DEV int wave_low(const uint32_t *x, int n)
 
 // The head of one instance with h, k = prec(v) - 1 and vlow (index of v's
 // lowest nonzero limb), by one wave in its own LDS area (plan_head words):
-// for the general case with h - k >= 2 and v not a
-// power of B, Alg. 1's initial approximation and its Refine iterations while
-// the iterate is shorter than kn.small_limit limbs, recorded in rec[0, nrec);
-// otherwise (or when the state does not fit) rec[0] = 0.
+// for the general case with h - k >= 2 and v not a power of B, Alg. 1's
+// initial approximation and its Refine iterations while the iterate is
+// shorter than kn.small_limit limbs, recorded in rec[0, nrec); otherwise (or
+// when the state does not fit) rec[0] = 0.
 MP_DEV void head_refine(uint32_t *lds, int h, int k, int vlow, const uint32_t *v, uint32_t *rec, int nrec,
                         const Knobs &kn)
 {
