@@ -557,8 +557,10 @@ def set_knobs(args):
 
 def knobs_now():
     from paper_2606_06386_amd import binding
+    sl = binding.get_knob(binding.MP_KNOB_SMALL_LIMIT)
     return {"mfma_min": binding.get_knob(binding.MP_KNOB_MFMA_MIN),
-            "small_limit": binding.get_knob(binding.MP_KNOB_SMALL_LIMIT)}
+            "small_limit": "auto (136 with several rounds of workgroups, else 96)"
+            if sl == binding.MP_SMALL_LIMIT_AUTO else sl}
 
 
 def run_mixed(args):

@@ -168,17 +168,24 @@ mp_status_t mp_ragged_config(int32_t cls, int32_t threads, int32_t wgs_per_cu);
  *                        vector ALU (32x32->64-bit multiply-adds).  Default 64.
  *   MP_KNOB_SMALL_LIMIT  Alg. 1's initial approximation and the Refine
  *                        iterations whose iterate has fewer than this many
- *                        limbs (0..128) run in a separate head launch, one wave
+ *                        limbs (0..140) run in a separate head launch, one wave
  *                        per instance, before the per-instance workgroups do
  *                        the rest; the head leaves its state in the first
  *                        limbs of the instance's q (mp_shinv_batch: w) row,
  *                        which the final result then overwrites.  0 (or an
  *                        output row shorter than 16 limbs) runs every step in
- *                        the per-instance workgroups.  Default 96.
+ *                        the per-instance workgroups.  MP_SMALL_LIMIT_AUTO
+ *                        (the default) chooses per launch: 136 when the batch
+ *                        needs more than one round of per-instance workgroups
+ *                        on the device (the head runs all instances at once,
+ *                        so its longer iterations are paid once and saved in
+ *                        every round), 96 otherwise.
  * mp_set_knob returns MP_ERR_ARG for an unknown knob or a value out of range;
  * mp_get_knob returns the current value (-1 for an unknown knob).
  */
 enum { MP_KNOB_MFMA_MIN = 0, MP_KNOB_SMALL_LIMIT = 1 };
+/* MP_KNOB_SMALL_LIMIT value: chosen per launch (see above) */
+#define MP_SMALL_LIMIT_AUTO (-2)
 mp_status_t mp_set_knob(int32_t knob, int32_t value);
 int32_t mp_get_knob(int32_t knob);
 

@@ -22,6 +22,7 @@ EXPORTS = ("mp_mul_batch", "mp_shinv_batch", "mp_divrem_batch", "mp_divrem_ragge
            "mp_ragged_workspace_bytes",
            "mp_ragged_config", "mp_set_knob", "mp_get_knob", "mp_lds_bytes", "mp_status_str", "mp_max_limbs")
 MP_KNOB_MFMA_MIN, MP_KNOB_SMALL_LIMIT = 0, 1
+MP_SMALL_LIMIT_AUTO = -2          # the head limit chosen per launch
 MP_OP_MUL, MP_OP_DIVREM, MP_OP_SHINV = 0, 1, 2
 
 _lib = None

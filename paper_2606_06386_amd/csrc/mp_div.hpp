@@ -94,7 +94,12 @@ MP_HD Plan plan_div(int h, int k)
 // guards, and products (w * x: at most 4l + 9 limbs).  No matrix-core area:
 // operands this short run on the vector ALU.  Every use is guarded; an
 // iteration that would overrun returns false and the body does it instead.
-constexpr int kHeadMaxLimit = 128;   // largest small_limit: every head operand then fits kHeadMaxLimbs
+// The window's zero guards are those of the one-wave product: its reads of
+// strip [K0, K0 + 64) with rows [ilo, ihi) stay within 65 limbs below the
+// window and 63 above it.  Sized so that 16 heads share a compute unit's LDS
+// up to the largest limit.
+constexpr int kHeadMaxLimit = 140;   // largest small_limit: every head operand then fits kHeadMaxLimbs
+constexpr int kHeadPad = kLanes + 8; // zero guard on both sides of a head's window operand
 // (the longest one-wave linear operation of a head is bounded by capP, capX or
 // capW + l, all below 4 * limit + 8 limbs)
 static_assert(4 * kHeadMaxLimit + 8 <= kHeadMaxLimbs, "head operands must fit one wave's addsub");
@@ -114,8 +119,8 @@ MP_HD Plan plan_head(int limit, int vbase)
     p.offW = p.offV + p.capV;
     p.offX = p.offW + p.capW;
     p.offR = p.offX + p.capX + kXPad;
-    p.offSB = p.offR + kXPad + kPad;
-    p.offP = p.offSB + p.capSB + kPad;
+    p.offSB = p.offR + kXPad + kHeadPad;
+    p.offP = p.offSB + p.capSB + kHeadPad;
     p.total = p.offP + p.capP + 4;
     return p;
 }
@@ -492,7 +497,7 @@ MP_DEV void head_refine(uint32_t *lds, int h, int k, int vlow, const uint32_t *v
         }
     }
     for (int i = lane(); i < pl.capW; i += T) W[i] = 0u;
-    for (int i = lane() - kPad; i < pl.capSB + kPad; i += T) SB[i] = 0u;
+    for (int i = lane() - kHeadPad; i < pl.capSB + kHeadPad; i += T) SB[i] = 0u;
     int we = 0, nw = 0, sbext = 0, l = 2;
     MP_WSTAMP(2);
     refine_init<T>(ctl, V + (k - 1 - vbase), W, we, nw);

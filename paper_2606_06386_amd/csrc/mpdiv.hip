@@ -18,9 +18,33 @@ constexpr int kMaxLimbs = 8192;
 constexpr int kLdsWords = 160 * 1024 / 4;   // gfx950: 160 KB of LDS per workgroup
 
 // run-time knobs (mp_set_knob)
-std::atomic<int32_t> g_mfma_min{64}, g_small_limit{96};
+std::atomic<int32_t> g_mfma_min{64}, g_small_limit{MP_SMALL_LIMIT_AUTO};
 
-mp::Knobs knobs() { return mp::Knobs{g_mfma_min.load(), g_small_limit.load()}; }
+// Head limits of the automatic setting.  The head runs every instance of a
+// batch at once (one wave each), the bodies in rounds of workgroups; moving
+// the Refine iteration whose iterate is ~130 limbs into the head costs its
+// latency once and saves it in every body round, so it pays from two rounds
+// on.
+constexpr int kSmallOneRound = 96, kSmallRounds = 136;
+static_assert(kSmallRounds <= mp::kHeadMaxLimit, "automatic head limit out of range");
+
+int device_cus();
+
+// the knobs of a launch whose body workgroups of T threads use `bytes` of LDS,
+// for `count` instances (the automatic head limit resolved)
+mp::Knobs knobs_for(int T, size_t bytes, int64_t count)
+{
+    int sl = g_small_limit.load();
+    if (sl == MP_SMALL_LIMIT_AUTO) {
+        const int cus = device_cus();
+        int per_cu = 16 / (T / 64);                 // four waves per SIMD
+        const int by_lds = bytes ? (int)(160 * 1024 / bytes) : per_cu;
+        per_cu = per_cu < by_lds ? per_cu : by_lds;
+        const int64_t slots = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+        sl = count > slots ? kSmallRounds : kSmallOneRound;
+    }
+    return mp::Knobs{g_mfma_min.load(), sl};
+}
 
 // a head kernel runs first when it has iterations to do and an output row can
 // hold a record with at least a few limbs (rows too short get none and the
@@ -181,7 +205,9 @@ mp_status_t ragged_launch(const uint32_t *u_pool, int64_t u_limbs, const uint32_
 {
     const int cus = device_cus();
     if (cus <= 0) return MP_ERR_DEVICE;
-    const mp::Knobs kn = knobs();
+    // (the automatic head limit counts rounds of the narrowest class's workgroups)
+    static const size_t narrow_bytes = (size_t)mp::div_lds_words(kClassWidth[0], kClassWidth[0], 256) * 4;
+    const mp::Knobs kn = knobs_for(256, narrow_bytes, count);
     hipLaunchKernelGGL(k_ragged_prep, dim3(1), dim3(1024), 0, st, desc, count, u_limbs, v_limbs, q_limbs,
                        r_limbs, inst_status, ws);
     if (hipGetLastError() != hipSuccess) return MP_ERR_LAUNCH;
@@ -252,7 +278,7 @@ mp_status_t mp_set_knob(int32_t knob, int32_t value)
         g_mfma_min.store(value);
         return MP_OK;
     case MP_KNOB_SMALL_LIMIT:
-        if (value < 0 || value > mp::kHeadMaxLimit) return MP_ERR_ARG;
+        if (value != MP_SMALL_LIMIT_AUTO && (value < 0 || value > mp::kHeadMaxLimit)) return MP_ERR_ARG;
         g_small_limit.store(value);
         return MP_OK;
     }
@@ -296,7 +322,7 @@ mp_status_t mp_mul_batch(const uint32_t *a, int32_t na, const uint32_t *b, int32
     if (words > kLdsWords) return MP_ERR_SIZE;
     const size_t bytes = (size_t)words * 4;
     hipStream_t st = (hipStream_t)stream;
-    const mp::Knobs kn = knobs();
+    const mp::Knobs kn = knobs_for(threads_for((na + nb + 1) / 2), bytes, batch);
     switch (threads_for((na + nb + 1) / 2)) {
     case 256: return status_of(mp::launch_mul<256>(batch, bytes, st, a, na, b, nb, c, kn));
     case 512: return status_of(mp::launch_mul<512>(batch, bytes, st, a, na, b, nb, c, kn));
@@ -318,7 +344,7 @@ mp_status_t mp_shinv_batch(const uint32_t *v, int32_t nv, int32_t h, uint32_t *w
     if (words > kLdsWords) return MP_ERR_SIZE;
     const size_t bytes = (size_t)words * 4;
     hipStream_t st = (hipStream_t)stream;
-    const mp::Knobs kn = knobs();
+    const mp::Knobs kn = knobs_for(T, bytes, batch);
     const int head = use_head(kn, nw);
     if (head && mp::launch_head_shinv(st, v, nv, h, w, nw, batch, kn) != hipSuccess) return MP_ERR_LAUNCH;
     switch (T) {
@@ -341,7 +367,7 @@ mp_status_t mp_divrem_batch(const uint32_t *u, int32_t nu, const uint32_t *v, in
     if (words > kLdsWords) return MP_ERR_SIZE;
     const size_t bytes = (size_t)words * 4;
     hipStream_t st = (hipStream_t)stream;
-    const mp::Knobs kn = knobs();
+    const mp::Knobs kn = knobs_for(T, bytes, batch);
     const int head = use_head(kn, nq);
     if (head && mp::launch_head_divrem(st, u, nu, v, nv, q, nq, batch, kn) != hipSuccess) return MP_ERR_LAUNCH;
     switch (T) {

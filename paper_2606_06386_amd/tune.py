@@ -74,13 +74,17 @@ def _time(rb, reps):
     return e0.elapsed_time(e1) / reps
 
 
-SMALL_LIMITS = (32, 48, 64, 80, 96, 112, 128)
+AUTO = -2           # the library's per-launch head limit (MP_SMALL_LIMIT_AUTO)
+SMALL_LIMITS = (AUTO, 32, 48, 64, 80, 96, 112, 128, 136)
 MFMA_MINS = (32, 64, 96, 128)
+AUTO_SLACK = 1.01    # the per-launch setting is kept unless a fixed one is >1% faster
 
 
 def tune_knobs(count=1024, reps=3, log=None):
     """Time every (small_limit, mfma_min) pair on a seeded mixed batch (all four
-    width classes); installs and returns the fastest as {knob: value, 'ms': ms}."""
+    width classes); installs and returns the fastest as {knob: value, 'ms': ms}.
+    The per-launch head limit (AUTO) adapts to each batch's size, so it is
+    preferred over a fixed limit that is not clearly faster on this batch."""
     from . import binding, ragged
     m = I.config_c4(index=np.arange(0, 8 * count, 8))
     rb = binding.Ragged(ragged.pack(m["u"], m["v"]))
@@ -92,8 +96,11 @@ def tune_knobs(count=1024, reps=3, log=None):
             ms = _time(rb, reps)
             times.append((ms, sl, mm))
             if log:
-                log("knobs small_limit %d, mfma_min %d: %.3f ms" % (sl, mm, ms))
+                log("knobs small_limit %s, mfma_min %d: %.3f ms" % ("auto" if sl == AUTO else sl, mm, ms))
     ms, sl, mm = min(times)
+    auto_ms, _, auto_mm = min(t for t in times if t[1] == AUTO)
+    if auto_ms <= ms * AUTO_SLACK:
+        ms, sl, mm = auto_ms, AUTO, auto_mm
     binding.set_knob(binding.MP_KNOB_SMALL_LIMIT, sl)
     binding.set_knob(binding.MP_KNOB_MFMA_MIN, mm)
     return {"small_limit": sl, "mfma_min": mm, "ms": ms}

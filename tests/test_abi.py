@@ -100,17 +100,20 @@ def test_lds_plan_bounds(L):
 
 
 def test_knobs(L):
-    from paper_2606_06386_amd.binding import MP_ERR_ARG, MP_KNOB_MFMA_MIN, MP_KNOB_SMALL_LIMIT, MP_OK
+    from paper_2606_06386_amd.binding import (MP_ERR_ARG, MP_KNOB_MFMA_MIN, MP_KNOB_SMALL_LIMIT, MP_OK,
+                                              MP_SMALL_LIMIT_AUTO)
     m0, s0 = L.mp_get_knob(MP_KNOB_MFMA_MIN), L.mp_get_knob(MP_KNOB_SMALL_LIMIT)
-    assert m0 >= 1 and 0 <= s0 <= 256
+    assert m0 >= 1 and (0 <= s0 <= 140 or s0 == MP_SMALL_LIMIT_AUTO)
     try:
         assert L.mp_set_knob(MP_KNOB_MFMA_MIN, 1 << 30) == MP_OK
         assert L.mp_get_knob(MP_KNOB_MFMA_MIN) == 1 << 30
         assert L.mp_set_knob(MP_KNOB_MFMA_MIN, 0) == MP_ERR_ARG
-        assert L.mp_set_knob(MP_KNOB_SMALL_LIMIT, 257) == MP_ERR_ARG
+        assert L.mp_set_knob(MP_KNOB_SMALL_LIMIT, 141) == MP_ERR_ARG
         assert L.mp_set_knob(MP_KNOB_SMALL_LIMIT, -1) == MP_ERR_ARG
+        assert L.mp_set_knob(MP_KNOB_SMALL_LIMIT, 140) == MP_OK
+        assert L.mp_set_knob(MP_KNOB_SMALL_LIMIT, MP_SMALL_LIMIT_AUTO) == MP_OK
+        assert L.mp_get_knob(MP_KNOB_SMALL_LIMIT) == MP_SMALL_LIMIT_AUTO
         assert L.mp_set_knob(9, 1) == MP_ERR_ARG and L.mp_get_knob(9) == -1
-        assert L.mp_get_knob(MP_KNOB_SMALL_LIMIT) == s0
     finally:
         L.mp_set_knob(MP_KNOB_MFMA_MIN, m0)
         L.mp_set_knob(MP_KNOB_SMALL_LIMIT, s0)

@@ -18,7 +18,7 @@ B = 1 << 32
 
 # (small_limit, mfma_min): default, no head, short and long head iterations,
 # products on the vector ALU only, matrix cores from 16-limb operands
-SETTINGS = [(64, 64), (0, 64), (16, 64), (128, 64), (64, 1 << 20), (128, 16)]
+SETTINGS = [(64, 64), (0, 64), (16, 64), (128, 64), (140, 64), (64, 1 << 20), (136, 16)]
 
 
 @pytest.fixture(scope="module")
