@@ -107,3 +107,17 @@ def test_shinv_every_head_setting(mp, knobs, small):
         wo, so = oracle.shinv(v, h, nw=h + 1)
         assert (st.cpu().numpy() == so).all()
         assert (w.cpu().numpy().view(np.uint32) == wo).all(), f"shinv h={h} small={small}"
+
+
+def test_auto_head_limit_both_sides_of_one_round(mp, knobs):
+    """The automatic head limit picks 96 limbs for a batch whose bodies fit in
+    one round of workgroups and 136 for a larger one; batches just below and
+    just above that size give the oracle's bits, as do both fixed limits."""
+    import torch
+    slots = 4 * torch.cuda.get_device_properties(0).multi_processor_count   # body workgroups per round at 2^16 bits
+    for count in (slots, slots + 1):
+        i = np.arange(count)
+        c = I.config_c2(index=i)
+        for small in (mp.MP_SMALL_LIMIT_AUTO, 96, 136):
+            knobs(small, 64)
+            _check(mp, c["u"], c["v"], c["nq"], f"2^16 batch {count} small={small}")
