@@ -31,6 +31,8 @@ namespace mp {
 #define MP_BODY_WAVES 4
 #endif
 #define MP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(T == 256 ? MP_BODY_WAVES : 4, 8)))
+// heads: four waves per SIMD (16 per compute unit, which is also what their LDS allows)
+#define MP_HEAD_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4, 8)))
 
 // Workspace of a ragged batch (int32): [0, 4) instances per class, [4, 8)
 // queue heads, then one list of instance indices per class, each `count` long.
@@ -144,7 +146,7 @@ hipError_t launch_ragged(int grid, size_t lds, hipStream_t st, const uint32_t *u
 
 // Heads: wave w of workgroup b owns instance b * kHeadWaves + w and the
 // `words` LDS words at lds + w * words (no workgroup barrier anywhere).
-__global__ __launch_bounds__(kLanes * kHeadWaves) void k_head_divrem(const uint32_t *u, int nu, const uint32_t *v,
+__global__ __launch_bounds__(kLanes * kHeadWaves) MP_HEAD_OCCUPANCY void k_head_divrem(const uint32_t *u, int nu, const uint32_t *v,
                                                                       int nv, uint32_t *q, int nq, int batch,
                                                                       int words, Knobs kn)
 {
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(kLanes * kHeadWaves) void k_head_divrem(const uint3
     head_divrem(lds + w * words, u + j * nu, nu, v + j * nv, nv, q + j * nq, nq, kn);
 }
 
-__global__ __launch_bounds__(kLanes * kHeadWaves) void k_head_shinv(const uint32_t *v, int nv, int h, uint32_t *w,
+__global__ __launch_bounds__(kLanes * kHeadWaves) MP_HEAD_OCCUPANCY void k_head_shinv(const uint32_t *v, int nv, int h, uint32_t *w,
                                                                      int nw, int batch, int words, Knobs kn)
 {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(kLanes * kHeadWaves) void k_head_shinv(const uint32
 
 // heads of a ragged batch: wave g takes the g-th valid instance of the class
 // lists (the preparation kernel's buckets, in class order)
-__global__ __launch_bounds__(kLanes * kHeadWaves) void k_head_ragged(const uint32_t *up, const uint32_t *vp,
+__global__ __launch_bounds__(kLanes * kHeadWaves) MP_HEAD_OCCUPANCY void k_head_ragged(const uint32_t *up, const uint32_t *vp,
                                                                       const mp_desc_t *desc, uint32_t *qp,
                                                                       const int32_t *ws, int count, int words,
                                                                       Knobs kn)

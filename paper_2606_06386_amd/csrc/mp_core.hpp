@@ -39,6 +39,8 @@ constexpr int kCtlStrip = 96;    // 2 words per strip carry, up to 72 strips
 constexpr int kCtlBcast = 240;   // 16 broadcast scalars
 constexpr int kCtlWords = 256;
 constexpr int kMaxStrips = 72;
+constexpr int kHeadStrips = 4;  // strips of a head's products (one wave, short operands)
+constexpr int kHeadCtlWords = kCtlStrip + 2 * kHeadStrips;   // a head's control block (no broadcast slots)
 
 // barrier of the T threads working on an instance: the workgroup, or (T = 64)
 // a single wave, which needs no hardware barrier
@@ -870,7 +872,9 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
         // accumulator (its chain of products costs about what the LDS round
         // trip of the next step does)
         const int eA = imin(dhiA, dloB - 1);
-        for (; d + 3 <= eA; d += 4) {
+        // (one wave alone on an instance, a head, keeps one diagonal per step:
+        // its registers hold the vector-ALU product's state too)
+        for (; T > kLanes && d + 3 <= eA; d += 4) {
             const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
             const XRaw r2 = xraw(x0 - 8 * d - 16), r3 = xraw(x0 - 8 * d - 24);
             const Limb4 y0v = load4(yA - 4 * d), y1v = load4(yA - 4 * d - 4);
@@ -900,7 +904,7 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
         if (!two) return;
         // strip sb alone (from dloB on, if strip sa ended before it began)
         d = imax(d, dloB);
-        for (; d + 3 <= dhiB; d += 4) {
+        for (; T > kLanes && d + 3 <= dhiB; d += 4) {
             const XRaw r0 = xraw(x0 - 8 * d), r1 = xraw(x0 - 8 * d - 8);
             const XRaw r2 = xraw(x0 - 8 * d - 16), r3 = xraw(x0 - 8 * d - 24);
             const Limb4 y0v = load4(yB - 4 * d), y1v = load4(yB - 4 * d - 4);
@@ -920,7 +924,9 @@ MP_DEV int mul_mfma(uint32_t *ctl, uint32_t *p, int ncols, const uint32_t *yb, i
         mfma_strip_out(ctl, accB, sb, base, p, c0, ncols);
     };
     const int npairs = (nstrips + 1) >> 1;
-    if (npairs >= 2 * W) {
+    if constexpr (T == kLanes) {
+        for (int s = 0; s < nstrips; s++) step(s, nstrips);   // one accumulator live at a time
+    } else if (npairs >= 2 * W) {
         for (int q = w; q < npairs; q += W) step(2 * q, 2 * q + 1);
     } else {
         for (int s = w; s < nstrips; s += 2 * W) step(s, s + W);

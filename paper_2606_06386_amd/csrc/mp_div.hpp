@@ -44,8 +44,8 @@ enum : int32_t { kInstOk = 0, kInstDivZero = 1, kInstQWidth = 2, kInstInternal =
 
 #define MP_HD __host__ __device__ __forceinline__
 
-MP_HD int r4(int x) { return (x + 3) & ~3; }
-MP_HD int hmax(int a, int b) { return a > b ? a : b; }
+MP_HD constexpr int r4(int x) { return (x + 3) & ~3; }
+MP_HD constexpr int hmax(int a, int b) { return a > b ? a : b; }
 
 // LDS layout of one division / shifted-inverse instance with h = prec(u)
 // (or the shinv precision) and k = prec(v) - 1, in 32-bit words.  Capacities
@@ -62,12 +62,14 @@ struct Plan {
     int capV, capW, capX, capR, capSB, capP;
     int offV, offW, offX, offR, offSB, offP;   // offR: word 0 of the reversed digits, offSB: limb 0 of the window
     int vbase;                                 // index of the divisor limb stored at offV (limbs below are not held)
+    int capY;          // longest operand whose matrix-core digit planes (with their zero pads) fit the window area
+    int sbLo, sbHi;    // the window area is SB[-sbLo, sbHi), kept zero where nothing is staged
     int total;
 };
 
-MP_HD Plan plan_div(int h, int k)
+MP_HD constexpr Plan plan_div(int h, int k)
 {
-    Plan p;
+    Plan p{};
     p.vbase = 0;
     const int d = h - k;
     p.capV = r4(k + 1);
@@ -83,44 +85,57 @@ MP_HD Plan plan_div(int h, int k)
     p.offSB = p.offR + p.capR + kXPad + kPad;
     p.offP = p.offSB + p.capSB + kPad;
     p.total = p.offP + p.capP + 4;
+    p.capY = 1 << 30;   // kPad covers the planes of any operand the window holds
+    p.sbLo = kPad;
+    p.sbHi = p.capSB + kPad;
     return p;
 }
 
 // LDS layout of one wave's head (the Refine iterations whose iterate has fewer
-// than `limit` limbs, so l <= limit - 4): the divisor limbs [vbase, k] it
-// reads (v' = v >> s has at most 2l + 2 limbs), the iterate (at most 2l + 2
-// limbs after the last of these iterations), PowDiff's residual (at most
-// 3l + 3 limbs, B^h' minus a product), the window operand with its zero
-// guards, and products (w * x: at most 4l + 9 limbs).  No matrix-core area:
-// operands this short run on the vector ALU.  Every use is guarded; an
-// iteration that would overrun returns false and the body does it instead.
-// The window's zero guards are those of the one-wave product: its reads of
-// strip [K0, K0 + 64) with rows [ilo, ihi) stay within 65 limbs below the
-// window and 63 above it.  Sized so that 16 heads share a compute unit's LDS
-// up to the largest limit.
+// than `limit` limbs, so l <= limit - 4): a short control block (a head's
+// products have at most kHeadStrips strips and it broadcasts nothing through
+// LDS), the divisor limbs [vbase, k] it reads (v' = v >> s has at most 2l + 2
+// limbs), the iterate (at most 2l + 2 limbs after the last of these
+// iterations), PowDiff's residual (at most 3l + 3 limbs, B^h' minus a
+// product), the reversed digits of a matrix-core product's shorter operand
+// (the iterate, at most l + 4 limbs), the window operand with its zero
+// guards, and products (w * x: at most 4l + 9 limbs).  Every use is guarded;
+// an iteration that would overrun returns false and the body does it instead.
+// The window's guards cover both product engines: the one-wave VALU product
+// reads strip [K0, K0 + 64) with rows [ilo, ihi) within 65 limbs below the
+// window and 63 above it; the matrix-core digit planes of a long operand of
+// up to capY = 2 limit + 8 limbs (v' and PowDiff's residual in the
+// iterations a head runs) need 4 kYPadBlk zero words below the window and
+// reach 8 ((capY + 8) / 8) + 8 kYPadBlk words above its start (a longer
+// operand takes the VALU product).  Sized so that 16 heads share a compute
+// unit's LDS up to the largest limit.
 constexpr int kHeadMaxLimit = 140;   // largest small_limit: every head operand then fits kHeadMaxLimbs
-constexpr int kHeadPad = kLanes + 8; // zero guard on both sides of a head's window operand
+constexpr int kHeadPad = kLanes + 8; // zero guard on both sides of a head's VALU window operand
 // (the longest one-wave linear operation of a head is bounded by capP, capX or
 // capW + l, all below 4 * limit + 8 limbs)
 static_assert(4 * kHeadMaxLimit + 8 <= kHeadMaxLimbs, "head operands must fit one wave's addsub");
+static_assert(4 * kHeadMaxLimit + 8 <= kHeadStrips * kStrip, "a head's products must fit its strip slots");
 
-MP_HD Plan plan_head(int limit, int vbase)
+MP_HD constexpr Plan plan_head(int limit, int vbase)
 {
-    Plan p;
+    Plan p{};
     const int L = limit < 4 ? 4 : limit > kHeadMaxLimit ? kHeadMaxLimit : limit;
     p.vbase = vbase;
     p.capV = r4(2 * L);
     p.capW = r4(2 * L + 8);
     p.capX = r4(3 * L + 8);
-    p.capR = 0;
+    p.capR = r4(L + 4);
     p.capSB = r4(3 * L + 8);
     p.capP = r4(4 * L + 8);
-    p.offV = kCtlWords;
+    p.capY = 2 * L + 8;
+    p.sbLo = hmax(kHeadPad, 4 * kYPadBlk);
+    p.sbHi = hmax(p.capSB + kHeadPad, 8 * ((p.capY + 8) >> 3) + 8 * kYPadBlk);
+    p.offV = kHeadCtlWords;
     p.offW = p.offV + p.capV;
     p.offX = p.offW + p.capW;
     p.offR = p.offX + p.capX + kXPad;
-    p.offSB = p.offR + kXPad + kHeadPad;
-    p.offP = p.offSB + p.capSB + kHeadPad;
+    p.offSB = p.offR + p.capR + kXPad + p.sbLo;
+    p.offP = p.offSB + p.sbHi;
     p.total = p.offP + p.capP + 4;
     return p;
 }
@@ -132,6 +147,7 @@ MP_HD Plan plan_head(int limit, int vbase)
 constexpr uint32_t kRecValid = 0x52454331u;
 constexpr int kRecHdr = 8;
 constexpr int kHeadWaves = 4;   // head instances (waves) per workgroup
+static_assert(16 * plan_head(kHeadMaxLimit, 0).total * 4 <= 160 * 1024, "16 heads must share a compute unit's LDS");
 
 // words needed by the single-limb-divisor path (quotient + chunk scratch)
 MP_HD int plan_short_words(int n, int T) { return kCtlWords + 2 * T + r4(n + 1) + 4; }
@@ -247,12 +263,15 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
     const int nvp = k + 1 - s;
     const int hp = H - m, lp = l - g;   // PowDiff(v', w, H - m, l - g)
     const int L = nvp + nw - lp + 1;
+    // a product goes to the matrix cores only if its longer operand's digit
+    // planes fit the window area
+    const int mm_pd = imax(nvp, nw) <= pl.capY ? kn.mfma_min : (1 << 30);
     bool sign;
     int nx;
     if (L >= hp) {                      // full product, compare with B^hp
         const int np0 = nvp + nw;
         if (np0 > pl.capP) return false;
-        const int np = product<T, MF>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR, kn.mfma_min);
+        const int np = product<T, MF>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR, mm_pd);
         if (np <= hp) {                 // P < B^hp: x = B^hp - P
             if (hp > pl.capX) return false;
             sign = true;
@@ -265,7 +284,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
         nx = read_prec<T>(ctl);
     } else {                            // close product: P = v'w mod B^L
         if (L > pl.capP || L > pl.capX) return false;
-        const int np = product<T, MF>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR, kn.mfma_min);
+        const int np = product<T, MF>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR, mm_pd);
         MP_STAMP(11);   // (trace build: sub-steps of the latest iteration)
         if (np == 0) {                  // v'w = B^hp exactly
             sign = true;
@@ -304,10 +323,11 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
         if (nt - cs > pl.capP) return false;
         // w is the shorter operand of both products on the matrix cores: its
         // digits from PowDiff's product are still in XR
-        const bool w_ready = MF && nvp >= nw && nw < nx && nw >= kn.mfma_min && nw + 1 <= pl.capR;
+        const bool w_ready = MF && nvp >= nw && nw < nx && nw >= mm_pd && nw + 1 <= pl.capR;
+        const int mm_st = imax(nw, nx) <= pl.capY ? kn.mfma_min : (1 << 30);
         MP_STAMP(12);
         // column c of the product goes to P[c - cs]
-        product<T, MF>(ctl, P - cs, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, kn.mfma_min, cs, false, w_ready);
+        product<T, MF>(ctl, P - cs, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, mm_st, cs, false, w_ready);
         MP_STAMP(13);
     }
     // the sticky borrow of the negative branch (any nonzero formed column
@@ -388,17 +408,19 @@ MP_DEV void refine_init(uint32_t *ctl, const uint32_t *vtop, uint32_t *W, int &w
         uint64_t w0;
         uint32_t w64;
         inv96_wave(Vt, w0, w64);
+        const uint32_t code = w64 ? 5u : (w0 >> 32) ? 4u : 3u;
         if (lane() == 0) {
             W[0] = 0u;
             W[1] = 0u;
             W[2] = (uint32_t)w0;
             W[3] = (uint32_t)(w0 >> 32);
             W[4] = w64;
-            ctl[kCtlBcast + 1] = w64 ? 5u : (w0 >> 32) ? 4u : 3u;
+            if constexpr (T > kLanes) ctl[kCtlBcast + 1] = code;
         }
+        if constexpr (T == kLanes) nw = (int)uniform(code);
     }
     bar<T>();
-    nw = (int)uniform(ctl[kCtlBcast + 1]);
+    if constexpr (T > kLanes) nw = (int)uniform(ctl[kCtlBcast + 1]);
     we = 5;
 }
 
@@ -497,14 +519,14 @@ MP_DEV void head_refine(uint32_t *lds, int h, int k, int vlow, const uint32_t *v
         }
     }
     for (int i = lane(); i < pl.capW; i += T) W[i] = 0u;
-    for (int i = lane() - kHeadPad; i < pl.capSB + kHeadPad; i += T) SB[i] = 0u;
+    for (int i = lane() - pl.sbLo; i < pl.sbHi; i += T) SB[i] = 0u;
     int we = 0, nw = 0, sbext = 0, l = 2;
     MP_WSTAMP(2);
     refine_init<T>(ctl, V + (k - 1 - vbase), W, we, nw);
     MP_WSTAMP(3);
     bool ok = true;
     for (int i = 0; i < ns && ok; i++) {
-        ok = refine_iter<T, false>(ctl, pl, kn, lds, h, k, i, l, we, nw, sbext);
+        ok = refine_iter<T>(ctl, pl, kn, lds, h, k, i, l, we, nw, sbext);
         MP_WSTAMP(16 + (i & 15));
     }
     ok = ok && kRecHdr + we <= nrec;
