@@ -474,6 +474,15 @@ def phase_trace(args):
                 continue
             head["iter_%d" % i] = float(np.mean(np.where(col > 0, col - prev_h, 0)))
             prev_h = np.where(col > 0, col, prev_h)
+        # sub-steps of iterations 3 and 6 (PowDiff product, residual, Step product, Step add)
+        for i, sl in ((3, 5), (6, 8)):
+            if "iter_%d" % i not in head or "iter_%d" % (i - 1) not in head:
+                continue
+            ok = (hr[:, [15 + i, sl, sl + 1, sl + 2, 16 + i]] > 0).all(axis=1)
+            if ok.any():
+                r = hr[ok]
+                t = [r[:, 15 + i], r[:, sl], r[:, sl + 1], r[:, sl + 2], r[:, 16 + i]]
+                head["iter_%d_steps" % i] = [float(np.mean(t[j + 1] - t[j])) for j in range(4)]
         head["record"] = float(np.mean(hr[:, 4] - prev_h))
         head["total"] = float(np.mean(hr[:, 4] - hr[:, 0]))
         head["span_all_waves"] = float(hr[:, 4].max() - hr[:, 0].min())

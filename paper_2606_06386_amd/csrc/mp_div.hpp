@@ -245,6 +245,16 @@ MP_DEV void store_zero(uint32_t *dst, int n)
 
 // ------------------------------------------------------- Alg. 1 Refine
 
+// (trace build: sub-steps of two of a head's iterations, i = 3 in slots 5-7
+// and i = 6 in slots 8-10: PowDiff's product, its residual, Step's product)
+#define MP_HEAD_SUB(i, k)                                       \
+    do {                                                        \
+        if constexpr (T == kLanes) {                            \
+            if ((i) == 3) MP_WSTAMP(5 + (k));                   \
+            else if ((i) == 6) MP_WSTAMP(8 + (k));              \
+        }                                                       \
+    } while (0)
+
 // Iteration i of the Refine loop (Alg. 1): PowDiff, then Step, updating the
 // iterate W (nonzero limbs inside [0, we), precision nw) and l.  Run by T
 // threads (the workgroup, or one wave in a head); MF as for product_views.
@@ -272,6 +282,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
         const int np0 = nvp + nw;
         if (np0 > pl.capP) return false;
         const int np = product<T, MF>(ctl, P, np0, vp, nvp, W, nw, SB, sbext, XR, pl.capR, mm_pd);
+        MP_HEAD_SUB(i, 0);
         if (np <= hp) {                 // P < B^hp: x = B^hp - P
             if (hp > pl.capX) return false;
             sign = true;
@@ -286,6 +297,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
         if (L > pl.capP || L > pl.capX) return false;
         const int np = product<T, MF>(ctl, P, L, vp, nvp, W, nw, SB, sbext, XR, pl.capR, mm_pd);
         MP_STAMP(11);   // (trace build: sub-steps of the latest iteration)
+        MP_HEAD_SUB(i, 0);
         if (np == 0) {                  // v'w = B^hp exactly
             sign = true;
             nx = 0;
@@ -310,6 +322,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
     // than 2^17 cs B^cs in size), so the formed sum T may exceed w x: one more
     // column holds T < 2 B^(nw+nx), and w x >= B^(nw+nx-2) >= B^(sh-1) keeps
     // T > 0.
+    MP_HEAD_SUB(i, 1);
     const int sh = H - 2 * m;
     const int post = i < 2 ? m : 1;
     int nt = 0, cs = 0;
@@ -330,6 +343,7 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
         product<T, MF>(ctl, P - cs, nt, W, nw, X, nx, SB, sbext, XR, pl.capR, mm_st, cs, false, w_ready);
         MP_STAMP(13);
     }
+    MP_HEAD_SUB(i, 2);
     // the sticky borrow of the negative branch (any nonzero formed column
     // below sh) is found by the Step's own addsub before its carry scan
     const int stop = !sign && nt > cs ? imin(sh, nt) - cs : 0;
@@ -424,6 +438,23 @@ MP_DEV void refine_init(uint32_t *ctl, const uint32_t *vtop, uint32_t *W, int &w
     we = 5;
 }
 
+// the same for one wave (a head) from V = v_{k-1} + v_k B held in registers
+MP_DEV void head_init(uint64_t Vt, uint32_t *W, int &we, int &nw)
+{
+    uint64_t w0;
+    uint32_t w64;
+    inv96_wave(Vt, w0, w64);
+    if (lane() == 0) {
+        W[0] = 0u;
+        W[1] = 0u;
+        W[2] = (uint32_t)w0;
+        W[3] = (uint32_t)(w0 >> 32);
+        W[4] = w64;
+    }
+    nw = (int)uniform(w64 ? 5u : (w0 >> 32) ? 4u : 3u);
+    we = 5;
+}
+
 // Initial approximation and the Refine loop for B^k <= v < B^(k+1), k >= 1,
 // h - k >= 1, B < v <= B^h / 2, v not a power of B.  v is in V (k+1 limbs),
 // W and the window area are zero.  With a valid head record `rec` (in global
@@ -488,15 +519,18 @@ MP_DEV int wave_low(const uint32_t *x, int n)
 // for the general case with h - k >= 2 and v not a power of B, Alg. 1's
 // initial approximation and its Refine iterations while the iterate is
 // shorter than kn.small_limit limbs, recorded in rec[0, nrec); otherwise (or
-// when the state does not fit) rec[0] = 0.
-MP_DEV void head_refine(uint32_t *lds, int h, int k, int vlow, const uint32_t *v, uint32_t *rec, int nrec,
-                        const Knobs &kn)
+// when the state does not fit) rec[0] = 0.  With have_top, vtop holds
+// v_{k-1} + v_k B (read by the caller), else they are read here.
+MP_DEV void head_refine(uint32_t *lds, int h, int k, int vlow, const uint32_t *v, uint64_t vtop, bool have_top,
+                        uint32_t *rec, int nrec, const Knobs &kn)
 {
     constexpr int T = kLanes;
     uint32_t *ctl = lds;
     const int d = h - k, g = 2;
     bool go = k >= 1 && d >= 2;
-    if (go) go = !(vlow == k && v[k] == 1u);
+    uint64_t Vt = vtop;
+    if (go && !have_top) Vt = ((uint64_t)v[k] << 32) | v[k - 1];
+    if (go) go = !(vlow == k && (uint32_t)(Vt >> 32) == 1u);
     const int ns = go ? small_iters(d, kn.small_limit) : 0;
     const int vbase = ns ? imax(0, k - 2 * refine_l(d, ns - 1) + 1 - g) : 0;
     const Plan pl = plan_head(kn.small_limit, vbase);
@@ -505,24 +539,26 @@ MP_DEV void head_refine(uint32_t *lds, int h, int k, int vlow, const uint32_t *v
         return;
     }
     uint32_t *V = lds + pl.offV, *W = lds + pl.offW, *SB = lds + pl.offSB;
-    // the divisor limbs [vbase, k]: four independent reads per lane in flight
-    // before their stores
-    {
-        const int nvs = k + 1 - vbase;
-        for (int i0 = lane(); i0 < nvs; i0 += 4 * T) {
-            uint32_t a[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) a[j] = i0 + j * T < nvs ? v[vbase + i0 + j * T] : 0u;
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                if (i0 + j * T < nvs) V[i0 + j * T] = a[j];
-        }
-    }
-    for (int i = lane(); i < pl.capW; i += T) W[i] = 0u;
-    for (int i = lane() - pl.sbLo; i < pl.sbHi; i += T) SB[i] = 0u;
+    // the divisor limbs [vbase, k] (at most capV <= 5 T): every read in flight
+    // at once; the LDS areas are zeroed and the initial approximation (from
+    // the top limbs in registers) computed while they arrive, then they are
+    // stored
     int we = 0, nw = 0, sbext = 0, l = 2;
-    MP_WSTAMP(2);
-    refine_init<T>(ctl, V + (k - 1 - vbase), W, we, nw);
+    {
+        static_assert(r4(2 * kHeadMaxLimit) <= 5 * T, "a head stages its divisor limbs in one round");
+        const int nvs = k + 1 - vbase;
+        uint32_t a[5];
+#pragma unroll
+        for (int j = 0; j < 5; j++) a[j] = lane() + j * T < nvs ? v[vbase + lane() + j * T] : 0u;
+        for (int i = lane(); i < pl.capW; i += T) W[i] = 0u;
+        for (int i = lane() - pl.sbLo; i < pl.sbHi; i += T) SB[i] = 0u;
+        wave_sync();
+        head_init(Vt, W, we, nw);
+#pragma unroll
+        for (int j = 0; j < 5; j++)
+            if (lane() + j * T < nvs) V[lane() + j * T] = a[j];
+    }
+    MP_WSTAMP(2);   // (trace build: staging and the initial approximation)
     MP_WSTAMP(3);
     bool ok = true;
     for (int i = 0; i < ns && ok; i++) {
@@ -567,6 +603,16 @@ MP_DEV void wave_vshape(const uint32_t *v, int nv, uint64_t mv, uint64_t mb, int
     vlow = mb ? __builtin_ctzll(mb) : wave_low(v, k + 1);
 }
 
+// v_{k-1} + v_k B from the registers of v's top 64 limbs (lane j holds limb
+// nv - 64 + j), when both limbs lie in that chunk
+MP_DEV bool wave_vtop(uint32_t vt, int nv, int k, uint64_t &V)
+{
+    const int j = k - (nv - kLanes);   // lane of v_k
+    if (k < 1 || j < 1 || j >= kLanes) return false;
+    V = ((uint64_t)readlane(vt, j) << 32) | readlane(vt, j - 1);
+    return true;
+}
+
 // the head of a division (h = prec(u), k = prec(v) - 1): the top 64 limbs of
 // u and of v and the bottom 64 of v are read together, which settles both
 // precisions and v's lowest nonzero limb in one round trip unless a number
@@ -581,8 +627,10 @@ MP_DEV void head_divrem(uint32_t *lds, const uint32_t *u, int nu, const uint32_t
     const int h = wave_prec_from(u, nu, mu);
     int k, vlow;
     wave_vshape(v, nv, mv, mb, k, vlow);
+    uint64_t vtop = 0;
+    const bool top = wave_vtop(vt, nv, k, vtop);
     MP_WSTAMP(1);
-    head_refine(lds, h, k, vlow, v, rec, nrec, kn);
+    head_refine(lds, h, k, vlow, v, vtop, top, rec, nrec, kn);
 }
 
 // the head of a shifted inverse floor(B^h / v)
@@ -592,7 +640,9 @@ MP_DEV void head_shinv(uint32_t *lds, int h, const uint32_t *v, int nv, uint32_t
     const uint32_t vt = iv >= 0 ? v[iv] : 0u, vb = il < nv ? v[il] : 0u;
     int k, vlow;
     wave_vshape(v, nv, ballot(vt != 0u), ballot(vb != 0u), k, vlow);
-    head_refine(lds, h, k, vlow, v, rec, nrec, kn);
+    uint64_t vtop = 0;
+    const bool top = wave_vtop(vt, nv, k, vtop);
+    head_refine(lds, h, k, vlow, v, vtop, top, rec, nrec, kn);
 }
 
 // a head record for (h, k) in the output row rec[0, nrec), or nullptr when rec
