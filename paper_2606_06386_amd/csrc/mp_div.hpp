@@ -358,6 +358,196 @@ MP_DEV bool refine_iter(uint32_t *ctl, const Plan &pl, const Knobs &kn, uint32_t
     return true;
 }
 
+// ------------------------------------------------ one-wave tiny iterations
+//
+// A Refine iteration whose operands, products and result all fit 64 limbs,
+// run by one wave with limb j of every intermediate in lane j: the same
+// arithmetic as refine_iter (the same products, the same clipping of the Step
+// product at cs, the same sticky borrow), with every carry resolved by the
+// ballot lookahead in registers instead of a pass through LDS.  Only the
+// divisor prefix and the iterate are read from LDS and only the new iterate is
+// written back.
+
+// the carry (or borrow) into each lane of a one-limb-per-lane addition
+// (subtraction) whose lanes generate g and propagate p, with carry-in cin;
+// cout gets the carry out of lane 63
+MP_DEV uint32_t lane_carry_in(bool g, bool p, uint32_t cin, uint32_t &cout)
+{
+    const uint64_t G = ballot(g), P = ballot(p), X = G | P;
+    const uint64_t s0 = X + G;
+    cout = (s0 < X ? 1u : 0u) | ((~P == 0 ? 1u : 0u) & cin);
+    const uint64_t cm = (X + G + (uint64_t)cin) ^ X ^ G;
+    return (uint32_t)(cm >> lane()) & 1u;
+}
+
+// a - b - bin in lanes [0, n) (zero above); bout: the borrow out of lane n - 1
+MP_DEV uint32_t lane_sub(uint32_t a, uint32_t b, int n, uint32_t bin, uint32_t &bout)
+{
+    const bool in = lane() < n;
+    const uint32_t d = in ? a - b : 0u;
+    const uint32_t bi = lane_carry_in(in && a < b, !in || d == 0u, bin, bout);
+    return in ? d - bi : 0u;
+}
+
+// a + b + cin in lanes [0, n) (zero above); cout: the carry out of lane n - 1
+MP_DEV uint32_t lane_add(uint32_t a, uint32_t b, int n, uint32_t cin, uint32_t &cout)
+{
+    const bool in = lane() < n;
+    const uint64_t s = (uint64_t)a + b;
+    const uint32_t z = in ? (uint32_t)s : 0u;
+    const uint32_t ci = lane_carry_in(in && (s >> 32) != 0, !in || z == 0xFFFFFFFFu, cin, cout);
+    return in ? z + ci : 0u;
+}
+
+// 1 + the highest lane holding a nonzero limb (0 when none)
+MP_DEV int lane_prec(uint32_t z)
+{
+    const uint64_t m = ballot(z != 0u);
+    return m ? 64 - __builtin_clzll(m) : 0;
+}
+
+// column K0 + lane of a * b with the carries between columns K0 .. K0 + 63
+// and none from below K0: rows a_i (i < na) from rowf(i) (wave-uniform i),
+// window limbs b_j (j < nb) from LDS, read per lane with a range mask
+template <class FR>
+MP_DEV uint32_t lane_mul(const FR &rowf, int na, const uint32_t *b, int nb, int K0)
+{
+    const int l = lane(), k = K0 + l;
+    const int ilo = imax(0, K0 - nb + 1), ihi = imin(na, K0 + kLanes);
+    uint64_t lo[4] = {0, 0, 0, 0};
+    uint32_t hi[4] = {0, 0, 0, 0};
+    for (int i = ilo; i < ihi; i += 4) {
+        uint32_t a[4], w[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            a[j] = i + j < ihi ? rowf(i + j) : 0u;
+            const int c = k - i - j;
+            w[j] = (unsigned)c < (unsigned)nb ? b[c] : 0u;
+        }
+        mac4x(lo, hi, a[0], w[0], a[1], w[1], a[2], w[2], a[3], w[3]);
+    }
+    uint64_t sl = lo[0];
+    uint32_t sh = hi[0];
+#pragma unroll
+    for (int r = 1; r < 4; r++) {
+        const uint64_t t = sl + lo[r];
+        sh += hi[r] + (t < sl ? 1u : 0u);
+        sl = t;
+    }
+    // S = s0 + s1 B + s2 B^2 per column: t = s0 + s1 of the lane below + s2 of the lane two below
+    const uint32_t s1m = shfl_up1((uint32_t)(sl >> 32)), s2m = shfl_up2(sh);
+    const uint64_t t = (uint64_t)(uint32_t)sl + s1m + s2m;
+    const uint32_t cm = shfl_up1((uint32_t)(t >> 32));
+    const uint64_t y = (uint64_t)(uint32_t)t + cm;
+    uint32_t dummy;
+    const uint32_t z = (uint32_t)y;
+    return z + lane_carry_in((y >> 32) != 0, z == 0xFFFFFFFFu, 0u, dummy);
+}
+
+struct LdsRows {
+    const uint32_t *p;
+    MP_DEV uint32_t operator()(int i) const { return p[i]; }
+};
+struct LaneRows {
+    uint32_t x;
+    MP_DEV uint32_t operator()(int i) const { return readlane(x, i); }
+};
+
+// whether Refine iteration i (with l, nw, we) fits one limb per lane throughout
+MP_DEV bool iter_fits_wave(const Plan &pl, int h, int k, int l, int nw, int we)
+{
+    const int g = 2, d = h - k;
+    const int m = imin(d + 1 - l, l);
+    const int s = imax(0, k - 2 * l + 1 - g);
+    const int H = k + l + m - s + g;
+    const int nvp = k + 1 - s;
+    const int hp = H - m, lp = l - g;
+    const int L = nvp + nw - lp + 1;
+    const int ncA = L >= hp ? nvp + nw : L;
+    const int nxmax = imax(ncA, hp);
+    const int sh = H - 2 * m;
+    const int cs = imax(sh - 2, 0) & ~7;
+    return s >= pl.vbase && ncA <= kLanes && hp <= kLanes && nw + nxmax + 1 - cs <= kLanes &&
+           imax(nw + m, nw + nxmax + 1 - sh) + 1 <= kLanes && we <= kLanes;
+}
+
+// Refine iteration i (as refine_iter) by one wave in registers, for an
+// iteration that iter_fits_wave accepts
+MP_DEV bool refine_iter_wave(const Plan &pl, uint32_t *lds, int h, int k, int i, int &l, int &we, int &nw)
+{
+    uint32_t *V = lds + pl.offV, *W = lds + pl.offW;
+    const int g = 2, d = h - k;
+    const int m = imin(d + 1 - l, l);
+    const int s = imax(0, k - 2 * l + 1 - g);
+    const int H = k + l + m - s + g;
+    const int nvp = k + 1 - s;
+    const int hp = H - m, lp = l - g;
+    const int L = nvp + nw - lp + 1;
+    const bool full = L >= hp;
+    const int ncA = full ? nvp + nw : L;          // columns PowDiff forms
+    const int sh = H - 2 * m;
+    const int cs = imax(sh - 2, 0) & ~7;
+    const int post = i < 2 ? m : 1;
+    const uint32_t *vp = V + (s - pl.vbase);
+    wave_sync();
+    const int ln = lane();
+    // PowDiff: P = v' w (all columns, or mod B^L), then x = |v' w - B^hp|
+    uint32_t P = lane_mul(LdsRows{W}, nw, vp, nvp, 0);
+    if (ln >= ncA) P = 0u;
+    const int np = lane_prec(P);
+    bool sign;
+    uint32_t x, bo;
+    if (full) {
+        if (np <= hp) {                 // x = B^hp - P
+            sign = true;
+            x = lane_sub(0u, P, hp, 0u, bo);
+        } else {                        // x = P - B^hp
+            sign = false;
+            x = lane_sub(P, ln == hp ? 1u : 0u, np, 0u, bo);
+        }
+    } else if (np == 0) {               // v'w = B^hp exactly
+        sign = true;
+        x = 0u;
+    } else if (np < L) {                // v'w = B^hp + P
+        sign = false;
+        x = P;
+    } else {                            // v'w = B^hp - (B^L - P)
+        sign = true;
+        x = lane_sub(0u, P, L, 0u, bo);
+    }
+    const int nx = lane_prec(x);
+    // Step: res = shift_m(w) +- shift_{2m-H}(w x), formed from column cs up
+    int nt = 0, cse = 0;
+    uint32_t below = 0, Ps = 0u;
+    if (nx && nw + nx <= sh) {
+        below = sign ? 0u : 1u;
+    } else if (nx) {
+        nt = nw + nx;
+        cse = cs;
+        if (cse) nt += 1;
+        Ps = lane_mul(LaneRows{x}, nx, W, nw, cse);
+        if (ln >= nt - cse) Ps = 0u;
+    }
+    const int stop = !sign && nt > cse ? imin(sh, nt) - cse : 0;
+    const bool sticky = ballot(ln < stop && Ps != 0u) != 0;
+    const int nres = imax(nw + m, nt - sh) + 1;
+    if (nres - post > pl.capW) return false;
+    const uint32_t wk = (unsigned)(ln - m) < (unsigned)nw ? W[ln - m] : 0u;
+    const int src = ln + sh - cse;   // column ln + sh of w x, at lane src of Ps
+    const uint32_t yk = __shfl(Ps, src < kLanes ? src : 0);
+    const uint32_t y = (src < kLanes && src < nt - cse) ? yk : 0u;
+    const uint32_t cin = sticky ? 1u : below;
+    uint32_t co;
+    const uint32_t res = sign ? lane_add(wk, y, nres, cin, co) : lane_sub(wk, y, nres, cin, co);
+    if (!sign && co) return false;
+    wave_sync();
+    if (ln >= post && ln < nres) W[ln - post] = res;
+    we = nres - post;
+    nw = imax(lane_prec(res) - post, 0);
+    if (i >= 2) l = l + m - 1;
+    return true;
+}
+
 MP_HD int refine_iters(int d)   // Alg. 1's iteration count for h - k = d >= 1
 {
     int r = 0;
@@ -561,7 +751,13 @@ MP_DEV void head_refine(uint32_t *lds, int h, int k, int vlow, const uint32_t *v
     MP_WSTAMP(2);   // (trace build: staging and the initial approximation)
     MP_WSTAMP(3);
     bool ok = true;
-    for (int i = 0; i < ns && ok; i++) {
+    int i = 0;
+    // the first iterations in registers, one limb per lane; the rest as in the body
+    for (; i < ns && ok && iter_fits_wave(pl, h, k, l, nw, we); i++) {
+        ok = refine_iter_wave(pl, lds, h, k, i, l, we, nw);
+        MP_WSTAMP(16 + (i & 15));
+    }
+    for (; i < ns && ok; i++) {
         ok = refine_iter<T>(ctl, pl, kn, lds, h, k, i, l, we, nw, sbext);
         MP_WSTAMP(16 + (i & 15));
     }
