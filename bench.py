@@ -373,6 +373,7 @@ PHASES = [("load_prec", 0, 1), ("setup", 1, 2), ("initial_approx", 2, 3), ("one_
 
 
 RT_HZ = 100e6   # rate of the real-time counter (s_memrealtime)
+kHEAD_WAVES = 4  # head instances (waves) per workgroup
 
 
 def clock_stats(c0, c1, r0, r1, event_ms=None):
@@ -483,6 +484,20 @@ def phase_trace(args):
                 r = hr[ok]
                 t = [r[:, 15 + i], r[:, sl], r[:, sl + 1], r[:, sl + 2], r[:, 16 + i]]
                 head["iter_%d_steps" % i] = [float(np.mean(t[j + 1] - t[j])) for j in range(4)]
+        # real-time stamps (100 MHz) at each head's start and end: the spread
+        # of starts (dispatch) and of durations behind the kernel's length
+        rt = hs[hfull][:, [14, 15]]
+        if (rt > 0).all():
+            st_us, en_us = (rt[:, 0] - rt[:, 0].min()) / RT_HZ * 1e6, (rt[:, 1] - rt[:, 0].min()) / RT_HZ * 1e6
+            dur = en_us - st_us
+            head["realtime_us"] = {"start_p50": float(np.percentile(st_us, 50)), "start_max": float(st_us.max()),
+                                   "duration_p50": float(np.percentile(dur, 50)),
+                                   "duration_p90": float(np.percentile(dur, 90)), "duration_max": float(dur.max()),
+                                   "end_max": float(en_us.max())}
+            # medians per quarter of the head workgroups, in launch order
+            wgq = (np.nonzero(hfull)[0] // kHEAD_WAVES) * 4 // max(1, -(-len(hs) // kHEAD_WAVES))
+            head["realtime_us"]["duration_p50_by_wg_quarter"] = [float(np.median(dur[wgq == r])) if (wgq == r).any()
+                                                                 else None for r in range(4)]
         head["record"] = float(np.mean(hr[:, 4] - prev_h))
         head["total"] = float(np.mean(hr[:, 4] - hr[:, 0]))
         head["span_all_waves"] = float(hr[:, 4].max() - hr[:, 0].min())

@@ -779,6 +779,7 @@ MP_DEV void head_refine(uint32_t *lds, int h, int k, int vlow, const uint32_t *v
         rec[0] = kRecValid;
     }
     MP_WSTAMP(4);
+    MP_WRSTAMP(15);   // (trace build: real time at the end and the start of a head)
 }
 
 // prec(x[0, n)) when x[0, n) is nonzero below its top 64 limbs or in them:
@@ -817,6 +818,7 @@ MP_DEV void head_divrem(uint32_t *lds, const uint32_t *u, int nu, const uint32_t
                         const Knobs &kn)
 {
     MP_WSTAMP(0);
+    MP_WRSTAMP(14);
     const int iu = nu - kLanes + lane(), iv = nv - kLanes + lane(), il = lane();
     const uint32_t ut = iu >= 0 ? u[iu] : 0u, vt = iv >= 0 ? v[iv] : 0u, vb = il < nv ? v[il] : 0u;
     const uint64_t mu = ballot(ut != 0u), mv = ballot(vt != 0u), mb = ballot(vb != 0u);

@@ -34,6 +34,12 @@ static __device__ uint64_t mp_trace_buf[8192 * 32];
         const size_t wv_ = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;                          \
         if ((threadIdx.x & 63) == 0 && wv_ < 8192) mp_trace_buf[wv_ * 32 + (id)] = __builtin_readcyclecounter(); \
     } while (0)
+// MP_WRSTAMP(id): the real-time counter for lane 0 of each wave (heads)
+#define MP_WRSTAMP(id)                                                                                         \
+    do {                                                                                                       \
+        const size_t wv_ = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;                          \
+        if ((threadIdx.x & 63) == 0 && wv_ < 8192) mp_trace_buf[wv_ * 32 + (id)] = __builtin_amdgcn_s_memrealtime(); \
+    } while (0)
 // Product trace: for each product an instance forms (up to 48), thread 0
 // records its shape and the shader clock at its start, after the digit
 // conversion (or window copy), after the first wave's strips and at its end,
@@ -91,6 +97,9 @@ __device__ __forceinline__ int &mp_ptrace_count()
     } while (0)
 #define MP_RSTAMP(id) \
     do {              \
+    } while (0)
+#define MP_WRSTAMP(id) \
+    do {               \
     } while (0)
 #endif
 
