@@ -736,8 +736,10 @@ def serving_compare(count=10000, rates=(1e6,), parity=True):
     from paper_2606_06386_amd import inputs as I, serve, tune
     tune.ensure(log=lambda m: print(m, file=sys.stderr, flush=True))
     ops = I.config_c5(1e3, count=count)
-    serving_run(1e5, 300, ops)                 # warm-up: first launches and allocations
-    serving_run(1e5, 300, ops, path="plain")
+    # warm-up at full size: first launches, the slot streams and the pinned
+    # request pools (a freshly pinned pool is slow on its first transfers)
+    serving_run(rates[0], count, ops)
+    serving_run(rates[0], count, ops, path="plain")
     out = {"workload": "serve_2p15_2p18_n%d" % count, "rates": []}
     for rate in rates:
         row_s, res = serving_run(rate, count, ops)

@@ -152,6 +152,21 @@ def device_budgets(req, depth, lds_waves=2.0, hbm_share=0.5):
     return {"hbm": (nbytes, free * hbm_share / depth), "lds": (lds, lds_waves)}
 
 
+_slot_streams = {}
+
+
+def slot_stream(device, path, slot):
+    """The stream of in-flight slot `slot` of a serving path on `device`,
+    shared by every backend of that path in the process: mp_divrem_ragged makes its fork streams once per
+    caller stream, on first use, so reusing the slot streams keeps that set-up
+    out of the serving loop of every run after the first."""
+    import torch
+    key = (str(device), path, int(slot))
+    if key not in _slot_streams:
+        _slot_streams[key] = torch.cuda.Stream(device=device)
+    return _slot_streams[key]
+
+
 class RaggedBackend:
     """Each batch is one mp_divrem_ragged call on the slot's own stream:
     operands up from pinned host memory, results back to it."""
@@ -167,9 +182,9 @@ class RaggedBackend:
         cap_v = int(min(slot_bytes // 4, req.vo[-1])) + 4
         nb = int(binding.lib().mp_ragged_workspace_bytes(max_batch))
         self.slots = []
-        for _ in range(depth):
+        for i in range(depth):
             self.slots.append({
-                "stream": torch.cuda.Stream(device=device),
+                "stream": slot_stream(device, "ragged", i),
                 "u": torch.empty(cap_u, dtype=torch.int32, device=device),
                 "v": torch.empty(cap_v, dtype=torch.int32, device=device),
                 "q": torch.empty(cap_u, dtype=torch.int32, device=device),
@@ -228,9 +243,9 @@ class PlainBackend:
         self.cls = np.array([width_class(n) for n in req.nu])
         cap = int(min(slot_bytes // 4, 2 * CLASS_WIDTHS[-1] * max_batch)) + 8
         self.slots = []
-        for _ in range(depth):
+        for i in range(depth):
             self.slots.append({
-                "stream": torch.cuda.Stream(device=device),
+                "stream": slot_stream(device, "plain", i),
                 "in_h": torch.empty(cap, dtype=torch.int32).pin_memory(),
                 "out_h": torch.empty(cap, dtype=torch.int32).pin_memory(),
                 "in_d": torch.empty(cap, dtype=torch.int32, device=device),
