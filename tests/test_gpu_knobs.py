@@ -121,3 +121,27 @@ def test_auto_head_limit_both_sides_of_one_round(mp, knobs):
         for small in (mp.MP_SMALL_LIMIT_AUTO, 96, 136):
             knobs(small, 64)
             _check(mp, c["u"], c["v"], c["nq"], f"2^16 batch {count} small={small}")
+
+
+@pytest.mark.parametrize("small", ["auto", 140, 64, 24])
+def test_head_register_iterations_every_boundary(mp, knobs, small):
+    """The head runs a Refine iteration in registers (one limb per lane) while
+    v', the iterate, PowDiff's product and residual, the Step product and the
+    new iterate all fit 64 limbs, and passes through LDS after that; divisor
+    lengths 2..71 limbs and quotient lengths 2..130 limbs put the switch at
+    every iteration, with random and structured divisors."""
+    knobs(mp.MP_SMALL_LIMIT_AUTO if small == "auto" else small, 64)
+    rng = random.Random(23)
+    width = 208
+    us, vs = [], []
+    for k in range(1, 71, 3):
+        for d in (2, 3, 5, 9, 17, 33, 65, 130):
+            if k + 1 + d > width:
+                continue
+            for v in (rng.getrandbits(32 * (k + 1)) | (1 << (32 * (k + 1) - 1)), B ** k + 1, B ** (k + 1) - 1):
+                u = rng.getrandbits(32 * (k + d)) | (1 << (32 * (k + d) - 1))
+                us.append(u)
+                vs.append(v)
+    u = np.stack([I.from_int(a, width) for a in us])
+    v = np.stack([I.from_int(b, width) for b in vs])
+    _check(mp, u, v, width, f"head boundary sweep small={small}")
