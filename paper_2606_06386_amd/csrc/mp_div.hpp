@@ -439,9 +439,9 @@ MP_DEV uint32_t lane_mul(const FR &rowf, int na, const uint32_t *b, int nb, int 
     const uint64_t t = (uint64_t)(uint32_t)sl + s1m + s2m;
     const uint32_t cm = shfl_up1((uint32_t)(t >> 32));
     const uint64_t y = (uint64_t)(uint32_t)t + cm;
-    uint32_t dummy;
+    uint32_t top_carry;   // leaves column K0 + 63: above every column a caller keeps
     const uint32_t z = (uint32_t)y;
-    return z + lane_carry_in((y >> 32) != 0, z == 0xFFFFFFFFu, 0u, dummy);
+    return z + lane_carry_in((y >> 32) != 0, z == 0xFFFFFFFFu, 0u, top_carry);
 }
 
 struct LdsRows {
@@ -534,7 +534,7 @@ MP_DEV bool refine_iter_wave(const Plan &pl, uint32_t *lds, int h, int k, int i,
     if (nres - post > pl.capW) return false;
     const uint32_t wk = (unsigned)(ln - m) < (unsigned)nw ? W[ln - m] : 0u;
     const int src = ln + sh - cse;   // column ln + sh of w x, at lane src of Ps
-    const uint32_t yk = __shfl(Ps, src < kLanes ? src : 0);
+    const uint32_t yk = shfl(Ps, src < kLanes ? src : 0);
     const uint32_t y = (src < kLanes && src < nt - cse) ? yk : 0u;
     const uint32_t cin = sticky ? 1u : below;
     uint32_t co;
